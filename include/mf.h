@@ -1,0 +1,186 @@
+/*
+ * mf.h -- C ABI of the MI355X (gfx950) MUSTA-FORCE library for ideal
+ * relativistic hydrodynamics.
+ *
+ * The library advances the conservation law dU/dt + dF/dx + dG/dy + dH/dz = 0
+ * of Porter-Sobieraj et al., "A MUSTA-FORCE algorithm for solving partial
+ * differential equations of relativistic hydrodynamics" (arXiv:1510.06340,
+ * Sec. 2.1, conservation law and flux vectors), with U = (E, Mx, My, Mz),
+ * by the dimensionally split scheme of Sec. 2.3-2.6: slope-limited MUSCL
+ * reconstruction, a Hancock half step, a k-stage MUSTA predictor-corrector
+ * with the FORCE centred flux on every interface, conserved-to-primitive
+ * recovery and a TVD Runge-Kutta update.
+ *
+ * Conventions
+ *  - Every call returns an int status: MF_OK (0) or a negative MF_ERR_*;
+ *    mf_last_error() returns a message for the calling thread's last error.
+ *  - State arrays are caller-owned device buffers (e.g. torch tensors), one
+ *    array per conserved component, x fastest: cell (i, j, k) is element
+ *    i + n[0] * (j + n[1] * k).  Their pointers are lent to the handle for
+ *    its lifetime; the library never frees them.
+ *  - Library-owned device scratch (Runge-Kutta stage states, the flux
+ *    accumulator, statistics) is allocated by mf_grid_init and released by
+ *    mf_grid_free.
+ *  - Work is enqueued on the stream given to mf_grid_init (a hipStream_t;
+ *    NULL = the default stream).  Calls that return host data synchronise
+ *    that stream before returning.
+ *  - Not thread-safe per handle: calls on one handle must not overlap.
+ */
+#ifndef MF_H
+#define MF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define MF_OK 0
+#define MF_ERR_ARG (-1)         /* invalid argument (sizes, pointers, codes) */
+#define MF_ERR_NOMEM (-2)       /* device or host allocation failed */
+#define MF_ERR_HIP (-3)         /* a HIP runtime call or kernel launch failed */
+#define MF_ERR_STATE (-4)       /* call out of order (e.g. no EoS set) */
+#define MF_ERR_UNPHYSICAL (-5)  /* MF_FLAG_STRICT and an unphysical state was met */
+#define MF_ERR_CFL (-6)         /* MF_FLAG_STRICT and alpha * Courant number > 1 */
+
+/* ---- codes ------------------------------------------------------------ */
+enum mf_bc { MF_BC_OUTFLOW = 0, MF_BC_PERIODIC = 1 };
+enum mf_dtype { MF_F64 = 0, MF_F32 = 1 };
+enum mf_limiter {
+    MF_LIM_NONE = 0,      /* central slope (U_{i+1} - U_{i-1}) / 2 */
+    MF_LIM_MINMOD = 1,    /* Minbee  xi(r) = max(0, min(1, r)) */
+    MF_LIM_SUPERBEE = 2,  /* xi(r) = max(0, min(2r, 1), min(r, 2)) */
+    MF_LIM_MC = 3,        /* monotonised central xi(r) = max(0, min(2r, (1+r)/2, 2)) */
+    MF_LIM_VANLEER = 4,   /* xi(r) = (r + |r|) / (1 + |r|) */
+    MF_LIM_VANALBADA = 5  /* xi(r) = (r^2 + r) / (r^2 + 1) */
+};
+enum mf_eos_kind { MF_EOS_IDEAL = 0, MF_EOS_TABLE = 1 };
+enum mf_c2p_mode { MF_C2P_PLAIN = 0, MF_C2P_SEEDED = 1 };
+
+#define MF_FLAG_STRICT 1u  /* mf_step fails on unphysical states or alpha*Courant > 1 */
+
+typedef struct mf_grid_s* mf_grid_t;
+
+/* One event (one grid).  Sec. 2.4: alpha = 3 in three dimensions. */
+typedef struct {
+    int32_t n[3];       /* cells along x, y, z (each >= 1) */
+    double dx[3];       /* cell sizes (> 0) */
+    double origin[3];   /* lower box corner; cell centres at origin + (i + 1/2) dx */
+    int32_t bc[3];      /* mf_bc per axis */
+    int32_t dtype;      /* mf_dtype of the state arrays and of the arithmetic */
+    int32_t limiter;    /* mf_limiter */
+    int32_t musta_k;    /* MUSTA stages k >= 1 (k = 1 is plain FORCE) */
+    int32_t rk_order;   /* 2 or 3 (Sec. 2.3) */
+    double alpha;       /* FORCE coefficient (> 0) */
+    uint32_t flags;     /* MF_FLAG_* */
+} mf_grid_desc;
+
+/* Per-event statistics of one mf_step / mf_batch_step call. */
+typedef struct {
+    double t;             /* event time after the call */
+    int64_t steps;        /* steps taken by this event since mf_grid_init */
+    double smax;          /* max |characteristic speed| over cells, axes and end-of-step states */
+    double courant;       /* smax * dt / min(dx) */
+    double totals[4];     /* sum over cells of (E, Mx, My, Mz) * dV of the final state */
+    int64_t n_floor;      /* con2prim calls whose |M| was clamped to (1 - 1e-12) E */
+    int64_t n_bad;        /* con2prim calls with E <= 0 or non-finite input */
+    int64_t newton_iters; /* Newton / bisection iterations of the table EoS */
+    int64_t n_fallback;   /* seeded con2prim calls that fell back to the plain solve */
+} mf_stats;
+
+/* Optional learned con2prim seed for MF_EOS_TABLE: a 2 -> H -> H -> 1 tanh
+ * MLP on x = ((ln E - in_shift[0]) * in_scale[0], (|M|/E - in_shift[1]) * in_scale[1])
+ * predicting ln e = out_scale * y + out_shift.  Weights row-major, host
+ * pointers, copied by mf_set_eos and rounded to bfloat16 on the device. */
+typedef struct {
+    int32_t hidden;      /* H (multiple of 16, <= 256) */
+    const float* w1;     /* H x 2 */
+    const float* b1;     /* H */
+    const float* w2;     /* H x H */
+    const float* b2;     /* H */
+    const float* w3;     /* 1 x H */
+    float b3;
+    float in_shift[2], in_scale[2];
+    float out_shift, out_scale;
+    int32_t max_newton;  /* seeded Newton iterations before the plain fallback (e.g. 3) */
+} mf_surrogate;
+
+/* Create a handle for n_events independent grids (Sec. 2.1 problem statement,
+ * one descriptor per event).  U_dev holds 4 device pointers per event
+ * (E, Mx, My, Mz, each n[0]*n[1]*n[2] elements of the event's dtype).
+ * stream: hipStream_t or NULL.  Errors: MF_ERR_ARG (n < 1, dx <= 0, k < 1,
+ * rk not 2/3, alpha <= 0, unknown codes, NULL pointers), MF_ERR_NOMEM, MF_ERR_HIP. */
+int mf_grid_init(mf_grid_t* out, const mf_grid_desc* descs, int32_t n_events,
+                 void* const* U_dev, void* stream);
+
+/* Equation of state p(e) (Sec. 2.1, closure p = p(e, n) without charge).
+ * MF_EOS_IDEAL: p = cs2 * e with 0 < cs2 < 1; the table arguments are ignored.
+ * MF_EOS_TABLE: n_tab >= 2 host nodes (e_tab strictly increasing, > 0;
+ * p_tab non-decreasing, >= 0, p < e) interpolated by a monotone piecewise
+ * cubic; below e_tab[0] p = p_tab[0] e / e_tab[0], above the last node linear
+ * with the end slope.  Fast interval lookup assumes log-uniform nodes and
+ * falls back to bisection otherwise.  s (nullable) attaches the learned seed.
+ * Host arrays are copied.  Errors: MF_ERR_ARG. */
+int mf_set_eos(mf_grid_t g, int32_t kind, double cs2, const double* e_tab,
+               const double* p_tab, int32_t n_tab, const mf_surrogate* s);
+
+/* Moving point-jet source for one event: adds to dE/dt and dMx/dt
+ * S = v dEdx G_sigma(x - x0 - v t e_x) (1, v, 0, 0), G_sigma the normalised
+ * 3-D Gaussian of width sigma sampled at cell centres.  0 < v < 1, sigma > 0;
+ * dEdx = 0 switches it off. */
+int mf_set_source_jet(mf_grid_t g, int32_t event, const double x0[3], double v,
+                      double dEdx, double sigma);
+
+/* Set an event's time t (used by the source term; resume from a checkpoint). */
+int mf_set_time(mf_grid_t g, int32_t event, double t, int64_t steps);
+
+/* Advance every event by nsteps Runge-Kutta steps of size dt (Sec. 2.3), one
+ * event after another.  st (nullable) receives n_events entries; passing it
+ * synchronises the stream.  Unphysical states are clamped and counted; with
+ * MF_FLAG_STRICT they make the call return MF_ERR_UNPHYSICAL, and
+ * alpha * Courant > 1 returns MF_ERR_CFL (the state is advanced either way).
+ * Errors: MF_ERR_STATE (no EoS), MF_ERR_ARG (dt <= 0, nsteps < 0), MF_ERR_HIP. */
+int mf_step(mf_grid_t g, double dt, int32_t nsteps, mf_stats* st);
+
+/* Advance all events together, event i by nsteps steps of size dt[i] (host
+ * array): each Runge-Kutta stage sweep is one persistent launch over a tile
+ * queue spanning every event, and a step is replayed from a captured HIP
+ * graph.  Results equal mf_step's per event.  st as in mf_step. */
+int mf_batch_step(mf_grid_t g, const double* dt, int32_t nsteps, mf_stats* st);
+
+/* Conserved -> primitive recovery (Sec. 2.6) of n states with the handle's
+ * EoS and dtype: U = 4 device arrays (E, Mx, My, Mz), prim = 5 device arrays
+ * (e, p, vx, vy, vz).  iters_dev (nullable, int32 device array of n) receives
+ * the root-finder iterations per state (0 for the closed form).  mode:
+ * MF_C2P_PLAIN or MF_C2P_SEEDED (needs a surrogate).  Asynchronous. */
+int mf_con2prim(mf_grid_t g, const void* const U[4], void* const prim[5], int64_t n,
+                int32_t* iters_dev, int32_t mode);
+
+/* Sums of (E, Mx, My, Mz) * dV over one event's cells (deterministic order).
+ * Synchronous. */
+int mf_totals(mf_grid_t g, int32_t event, double out[4]);
+
+/* Per-step kernel shape: cells per thread along each sweep axis (0 = automatic)
+ * and threads per block (64, 128 or 256).  Used by the autotuner. */
+int mf_set_tuning(mf_grid_t g, const int32_t seg[3], int32_t block);
+
+/* Kernel timing: with enable != 0 every axis-sweep launch is bracketed by
+ * HIP events on the handle's stream.  mf_get_profile synchronises the stream
+ * and returns, per sweep axis (x, y, z), the summed kernel time in
+ * milliseconds and the number of launches since profiling was enabled or
+ * last read; then it resets the counts. */
+int mf_set_profiling(mf_grid_t g, int32_t enable);
+int mf_get_profile(mf_grid_t g, double ms[3], int64_t launches[3]);
+
+/* Release the handle and its scratch (the caller's state arrays are untouched). */
+int mf_grid_free(mf_grid_t g);
+
+/* Message of the calling thread's last error ("" if none). */
+const char* mf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MF_H */

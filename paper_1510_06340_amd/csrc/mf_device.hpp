@@ -1,0 +1,259 @@
+// mf_device.hpp -- pointwise device building blocks of the MUSTA-FORCE step
+// for gfx950: conserved-to-primitive recovery, physical fluxes, slope
+// limiters, the Hancock half step and the MUSTA-FORCE interface flux.
+//
+// Everything here is register-resident and templated on the arithmetic type
+// T (double or float) and on the sweep axis D (0 = x, 1 = y, 2 = z).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mf_params.hpp"
+
+namespace mf {
+
+enum { LIM_NONE = 0, LIM_MINMOD, LIM_SUPERBEE, LIM_MC, LIM_VANLEER, LIM_VANALBADA };
+
+// ---------------------------------------------------------------------------
+// Reciprocal and square root.  FP64: the hardware estimates (v_rcp_f64,
+// v_rsq_f64) refined by Newton-Raphson steps in FMA, which is within an ulp of
+// the IEEE results for the normal, positive arguments met here (denominators
+// >= E > 0), without the scaling and fix-up code of the IEEE expansions.
+// FP32: the hardware instructions (about 1 ulp).
+// ---------------------------------------------------------------------------
+template <typename T> struct Math;
+
+template <> struct Math<double> {
+    static __device__ __forceinline__ double rcp(double x)
+    {
+        double r = __builtin_amdgcn_rcp(x);
+        double e = __builtin_fma(-x, r, 1.0);
+        r = __builtin_fma(r, e, r);
+        e = __builtin_fma(-x, r, 1.0);
+        return __builtin_fma(r, e, r);
+    }
+    static __device__ __forceinline__ double sqrt(double x)
+    {
+        double y = __builtin_amdgcn_rsq(x);
+        double g = x * y;          // sqrt(x) estimate
+        double h = 0.5 * y;        // 1 / (2 sqrt(x)) estimate
+        double r = __builtin_fma(-g, h, 0.5);
+        g = __builtin_fma(g, r, g);
+        h = __builtin_fma(h, r, h);
+        double d = __builtin_fma(-g, g, x);
+        return __builtin_fma(d, h, g);
+    }
+    // sqrt that also returns 0 for x == 0 (rsq(0) is +inf).
+    static __device__ __forceinline__ double sqrt0(double x) { return x > 0.0 ? sqrt(x) : 0.0; }
+    static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+};
+
+template <> struct Math<float> {
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float sqrt0(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+};
+
+template <typename T> __device__ __forceinline__ T big_value();
+template <> __device__ __forceinline__ double big_value<double>() { return 1.79769313486231570e308; }
+template <> __device__ __forceinline__ float big_value<float>() { return 3.40282347e38f; }
+
+// Largest admitted |M| / E; larger momenta are scaled down to it for the
+// evaluation (the stored state is not changed).
+template <typename T> __device__ __forceinline__ T mmax();
+template <> __device__ __forceinline__ double mmax<double>() { return 1.0 - 1e-12; }
+template <> __device__ __forceinline__ float mmax<float>() { return 1.0f - 1e-6f; }
+
+// Per-thread counters of guarded states, kept in registers.
+struct Counts {
+    uint32_t floor_ = 0;  // |M| clamped
+    uint32_t bad = 0;     // E <= 0 or non-finite
+    uint32_t iters = 0;   // root-finder iterations (table EoS)
+};
+
+// ---------------------------------------------------------------------------
+// Equations of state.  An EoS provides
+//   flux<D>(U, F, counts):  F = F_D(U) after con2prim,
+//   prim(U, e, p, v[3], cs2, counts): full primitive recovery.
+// ---------------------------------------------------------------------------
+
+// p = c e.  con2prim of the fixed point v = |M| / (E + p(E - |M| v)) is the
+// root below one of  c|M| v^2 - (1+c) E v + |M| = 0:
+//   v_vec = 2 M / ((1+c) E + sqrt((1+c)^2 E^2 - 4 c |M|^2)),  e = E - M.v.
+template <typename T> struct EosIdeal {
+    T c;   // cs2
+    T q;   // 1 + cs2
+    T q2;  // (1 + cs2)^2
+    T c4;  // 4 cs2
+
+    // Returns E (possibly replaced) and the momentum to use, applying the guards.
+    __device__ __forceinline__ void guard(T& E, T& Mx, T& My, T& Mz, T& M2, bool& bad,
+                                          Counts& cnt) const
+    {
+        M2 = Mx * Mx + My * My + Mz * Mz;
+        bad = !((E > T(0)) & (E <= big_value<T>()) & (M2 <= big_value<T>()));
+        if (bad) {
+            cnt.bad++;
+            E = T(1);
+            Mx = T(0); My = T(0); Mz = T(0); M2 = T(0);
+        }
+        const T Mlim = mmax<T>() * E;
+        if (M2 > Mlim * Mlim) {
+            const T s = Math<T>::div(Mlim, Math<T>::sqrt(M2));
+            Mx = Mx * s; My = My * s; Mz = Mz * s;
+            M2 = Mx * Mx + My * My + Mz * Mz;
+            cnt.floor_++;
+        }
+    }
+
+    template <int D>
+    __device__ __forceinline__ void flux(const T u[4], T F[4], Counts& cnt) const
+    {
+        T E = u[0], Mx = u[1], My = u[2], Mz = u[3], M2;
+        bool bad;
+        guard(E, Mx, My, Mz, M2, bad, cnt);
+        const T s = Math<T>::sqrt(q2 * E * E - c4 * M2);
+        const T r2 = T(2) * Math<T>::rcp(q * E + s);   // v_vec = r2 M
+        const T e = E - r2 * M2;                       // E - M.v
+        const T p = c * e;
+        const T MD = (D == 0) ? Mx : ((D == 1) ? My : Mz);
+        const T vD = r2 * MD;
+        F[0] = (E + p) * vD;
+        F[1] = Mx * vD;
+        F[2] = My * vD;
+        F[3] = Mz * vD;
+        F[1 + D] = F[1 + D] + p;
+        if (bad) { F[0] = T(0); F[1] = T(0); F[2] = T(0); F[3] = T(0); }
+    }
+
+    __device__ __forceinline__ void prim(const T u[4], T& e, T& p, T v[3], T& cs2,
+                                         Counts& cnt) const
+    {
+        T E = u[0], Mx = u[1], My = u[2], Mz = u[3], M2;
+        bool bad;
+        guard(E, Mx, My, Mz, M2, bad, cnt);
+        const T s = Math<T>::sqrt(q2 * E * E - c4 * M2);
+        const T r2 = T(2) * Math<T>::rcp(q * E + s);
+        v[0] = r2 * Mx; v[1] = r2 * My; v[2] = r2 * Mz;
+        e = E - (Mx * v[0] + My * v[1] + Mz * v[2]);
+        p = c * e;
+        cs2 = c;
+        if (bad) { e = T(0); p = T(0); v[0] = T(0); v[1] = T(0); v[2] = T(0); }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Slope limiters (Sec. 2.5) in the two-argument form phi(a, b) = xi(b/a) a,
+// a = U_i - U_{i-1}, b = U_{i+1} - U_i.  For the symmetric limiters of the
+// paper the left and right face slopes coincide, U^{L,R} = U -/+ phi / 2.
+// "Same sign" = both non-zero with equal signs (no product, which could
+// underflow).
+// ---------------------------------------------------------------------------
+template <int LIM, typename T>
+__device__ __forceinline__ T limiter(T a, T b)
+{
+    if constexpr (LIM == LIM_NONE) {
+        return T(0.5) * (a + b);
+    } else if constexpr (LIM == LIM_VANALBADA) {
+        const T den = a * a + b * b;
+        return (den > T(0)) ? (a * b * (a + b)) / den : T(0);
+    } else {
+        const bool same = (fmin(a, b) > T(0)) | (fmax(a, b) < T(0));
+        const T aa = fabs(a), bb = fabs(b);
+        T m;
+        if constexpr (LIM == LIM_MINMOD) {
+            m = fmin(aa, bb);
+        } else if constexpr (LIM == LIM_SUPERBEE) {
+            m = fmax(fmin(T(2) * bb, aa), fmin(bb, T(2) * aa));
+        } else if constexpr (LIM == LIM_MC) {
+            m = fmin(fmin(T(2) * aa, T(2) * bb), T(0.5) * fabs(a + b));
+        } else {  // LIM_VANLEER: 2ab / (a + b) = 2|a||b| / (|a| + |b|) for equal signs
+            m = Math<T>::div(T(2) * aa * bb, aa + bb);
+        }
+        return same ? copysign(m, a) : T(0);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// MUSCL reconstruction + Hancock half step for one cell along axis D
+// (Sec. 2.4: piecewise-linear cell profile, faces U^L = U - Delta/2,
+// U^R = U + Delta/2, both advanced by (dt/2dx)(F(U^L) - F(U^R))).
+// ---------------------------------------------------------------------------
+template <int D, int LIM, typename T, class Eos>
+__device__ __forceinline__ void hancock(const T um[4], const T u0[4], const T up[4], T half_lam,
+                                        T ULt[4], T URt[4], const Eos& eos, Counts& cnt)
+{
+    T UL[4], UR[4], FL[4], FR[4];
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        const T slope = limiter<LIM>(u0[c] - um[c], up[c] - u0[c]);
+        UL[c] = u0[c] - T(0.5) * slope;
+        UR[c] = u0[c] + T(0.5) * slope;
+    }
+    eos.template flux<D>(UL, FL, cnt);
+    eos.template flux<D>(UR, FR, cnt);
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        const T delta = half_lam * (FL[c] - FR[c]);
+        ULt[c] = UL[c] + delta;
+        URt[c] = UR[c] + delta;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// MUSTA-FORCE flux at one interface (Sec. 2.4): k stages of the FORCE flux
+//   F_lw = F(1/2 (U_L + U_R) - alpha dt/(2dx) (F_R - F_L))     (Richtmyer)
+//   F_lf = 1/2 (F_L + F_R) - dx/(2 alpha dt) (U_R - U_L)
+//   F    = 1/2 (F_lw + F_lf)
+// with the local predictor U_L -= dt/dx (F - F_L), U_R -= dt/dx (F_R - F)
+// between stages.  UL and UR are consumed.
+// ---------------------------------------------------------------------------
+template <int D, typename T, class Eos>
+__device__ __forceinline__ void musta(T UL[4], T UR[4], int k, const AxisConst<T>& ac, T F[4],
+                                      const Eos& eos, Counts& cnt)
+{
+    for (int l = 1;; l++) {
+        T FL[4], FR[4], Us[4], Flw[4];
+        eos.template flux<D>(UL, FL, cnt);
+        eos.template flux<D>(UR, FR, cnt);
+#pragma unroll
+        for (int c = 0; c < 4; c++) Us[c] = T(0.5) * (UL[c] + UR[c]) - ac.half_alam * (FR[c] - FL[c]);
+        eos.template flux<D>(Us, Flw, cnt);
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            const T Flf = T(0.5) * (FL[c] + FR[c]) - (UR[c] - UL[c]) * ac.inv_2alam;
+            F[c] = T(0.5) * (Flw[c] + Flf);
+        }
+        if (l >= k) break;
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            UL[c] = UL[c] - ac.lam * (F[c] - FL[c]);
+            UR[c] = UR[c] - ac.lam * (FR[c] - F[c]);
+        }
+    }
+}
+
+// Largest |characteristic speed| of a primitive state over the three axes:
+// lambda_pm = [v_d (1 - cs2) +- cs sqrt((1 - v^2)(1 - v_d^2 - (v^2 - v_d^2) cs2))] / (1 - v^2 cs2).
+template <typename T>
+__device__ __forceinline__ T max_speed(const T v[3], T cs2)
+{
+    const T v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    const T cs = Math<T>::sqrt(cs2);
+    const T inv = Math<T>::rcp(T(1) - v2 * cs2);
+    T s = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const T vd = v[d];
+        T rad = (T(1) - v2) * (T(1) - vd * vd - (v2 - vd * vd) * cs2);
+        rad = rad > T(0) ? rad : T(0);
+        const T root = cs * Math<T>::sqrt0(rad);
+        const T a = vd * (T(1) - cs2);
+        s = fmax(s, fmax(fabs((a + root) * inv), fabs((a - root) * inv)));
+    }
+    return s;
+}
+
+}  // namespace mf

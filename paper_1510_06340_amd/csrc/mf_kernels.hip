@@ -1,0 +1,352 @@
+// mf_kernels.hip -- gfx950 kernels of the MUSTA-FORCE step.
+//
+// Axis sweep (k_sweep): one thread owns a segment of one grid line along the
+// sweep axis and marches along it with a three-cell register window, so each
+// cell's reconstruction + Hancock half step and each interface's MUSTA-FORCE
+// flux is computed once (plus two cells and one interface of overlap per
+// segment).  Lanes of a wavefront own neighbouring lines: for the y and z
+// sweeps they are neighbouring x cells, so every load and store is one
+// contiguous 512-byte (FP64) row; for the x sweep they are neighbouring rows
+// and each lane's cache line is reused over the following steps of the march.
+// The three sweeps of a Runge-Kutta stage accumulate L = ((Lx + Ly) + Lz) in
+// a library-owned array; the z sweep also adds the source term, applies the
+// Runge-Kutta combine and (last stage) reduces the max characteristic speed.
+#include <hip/hip_runtime.h>
+
+#include "mf_device.hpp"
+#include "mf_kernels.hpp"
+
+namespace mf {
+
+template <typename T>
+__device__ __forceinline__ void load4(const T* const u[4], int64_t i, T w[4])
+{
+    w[0] = u[0][i]; w[1] = u[1][i]; w[2] = u[2][i]; w[3] = u[3][i];
+}
+
+template <typename T>
+__device__ __forceinline__ void copy4(const T a[4], T b[4])
+{
+    b[0] = a[0]; b[1] = a[1]; b[2] = a[2]; b[3] = a[3];
+}
+
+__device__ __forceinline__ void add_counts(Counts& a, const Counts& b)
+{
+    a.floor_ += b.floor_;
+    a.bad += b.bad;
+    a.iters += b.iters;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Flush per-thread counters and the speed maximum: one atomic per wavefront.
+template <typename T>
+__device__ __forceinline__ void flush_stats(unsigned long long* st, const Counts& cnt, T smax,
+                                            bool want_smax)
+{
+    const uint32_t f = wave_sum(cnt.floor_);
+    const uint32_t b = wave_sum(cnt.bad);
+    const uint32_t it = wave_sum(cnt.iters);
+    double sm = 0.0;
+    if (want_smax) sm = (double)wave_max(smax);
+    if ((threadIdx.x & 63) == 0) {
+        if (f) atomicAdd(&st[ST_FLOOR], (unsigned long long)f);
+        if (b) atomicAdd(&st[ST_BAD], (unsigned long long)b);
+        if (it) atomicAdd(&st[ST_ITERS], (unsigned long long)it);
+        if (want_smax && sm > 0.0) atomicMax(&st[ST_SMAX], (unsigned long long)__double_as_longlong(sm));
+    }
+}
+
+template <typename T, int D, int LIM, class Eos, bool JET>
+__global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a, Eos eos)
+{
+    const int64_t line = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int N = a.N;
+    const int s0 = blockIdx.y * a.seg;
+    Counts cnt;
+    T smax = T(0);
+    if (line < a.nlines && s0 < N) {
+        const int s1 = min(s0 + a.seg, N);
+        const int64_t i_f = line % a.n_fast;
+        const int64_t i_s = line / a.n_fast;
+        const int64_t base = i_f * a.stride_f + i_s * a.stride_s;
+        const int64_t sd = a.stride_d;
+        // ghost cells: outflow copies the edge cell, periodic wraps (N >= 2: one wrap suffices)
+        auto cell = [&](int j) -> int64_t {
+            int jj;
+            if (a.periodic) jj = (N == 1) ? 0 : (j < 0 ? j + N : (j >= N ? j - N : j));
+            else jj = j < 0 ? 0 : (j >= N ? N - 1 : j);
+            return base + (int64_t)jj * sd;
+        };
+
+        T w0[4], w1[4], w2[4];
+        T ULt[4], URt[4], URp[4], Fp[4], Fn[4];
+        load4(a.u, cell(s0 - 2), w0);
+        load4(a.u, cell(s0 - 1), w1);
+        load4(a.u, cell(s0), w2);
+        {   // cell s0 - 1 and interface s0 - 1/2 (owned by the segment only at the line start)
+            Counts c1;
+            hancock<D, LIM>(w0, w1, w2, a.ac.half_lam, ULt, URp, eos, c1);
+            copy4(w1, w0);
+            copy4(w2, w1);
+            load4(a.u, cell(s0 + 1), w2);
+            hancock<D, LIM>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, cnt);  // cell s0
+            musta<D>(URp, ULt, a.k, a.ac, Fp, eos, c1);
+            if (s0 == 0) add_counts(cnt, c1);
+            copy4(URt, URp);
+        }
+
+        for (int j = s0; j < s1; j++) {
+            copy4(w1, w0);
+            copy4(w2, w1);
+            load4(a.u, cell(j + 2), w2);
+            const int64_t ij = base + (int64_t)j * sd;
+            T Lp[4], ub[4];
+            if (a.mode != SW_WRITE) load4((const T* const*)a.L, ij, Lp);
+            if (a.mode == SW_FINAL && a.kind != RK_FIRST) load4(a.u0, ij, ub);
+
+            // cell j+1: owned unless it is the next segment's first cell
+            if (j + 1 < s1 || j + 1 == N) {
+                hancock<D, LIM>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, cnt);
+            } else {
+                Counts c2;
+                hancock<D, LIM>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, c2);
+            }
+            musta<D>(URp, ULt, a.k, a.ac, Fn, eos, cnt);  // interface j + 1/2
+
+            T Ld[4];
+#pragma unroll
+            for (int c = 0; c < 4; c++) Ld[c] = -(Fn[c] - Fp[c]) * a.ac.inv_dx;
+
+            if (a.mode == SW_WRITE) {
+#pragma unroll
+                for (int c = 0; c < 4; c++) a.L[c][ij] = Ld[c];
+            } else if (a.mode == SW_ACCUM) {
+#pragma unroll
+                for (int c = 0; c < 4; c++) a.L[c][ij] = Lp[c] + Ld[c];
+            } else {
+                T Lt[4];
+#pragma unroll
+                for (int c = 0; c < 4; c++) Lt[c] = Lp[c] + Ld[c];
+                if constexpr (JET) {
+                    double pos[3];
+                    pos[D] = a.origin[D] + (j + 0.5) * a.dx[D];
+                    pos[a.axis_f] = a.origin[a.axis_f] + (i_f + 0.5) * a.dx[a.axis_f];
+                    pos[a.axis_s] = a.origin[a.axis_s] + (i_s + 0.5) * a.dx[a.axis_s];
+                    const T x = T(pos[0] - a.jet_pos[0]);
+                    const T y = T(pos[1] - a.jet_pos[1]);
+                    const T z = T(pos[2] - a.jet_pos[2]);
+                    const T G = T(a.jet_norm) * exp(-(x * x + y * y + z * z) * T(a.jet_inv2s2));
+                    const T SE = T(a.jet_ve) * G;
+                    Lt[0] = Lt[0] + SE;
+                    Lt[1] = Lt[1] + T(a.jet_v) * SE;
+                }
+                const T* uin = w0;  // U[j] after the window shift
+                T o[4];
+                const T dt = a.dt;
+                if (a.kind == RK_FIRST) {
+#pragma unroll
+                    for (int c = 0; c < 4; c++) o[c] = uin[c] + dt * Lt[c];
+                } else if (a.kind == RK2_LAST) {
+#pragma unroll
+                    for (int c = 0; c < 4; c++) o[c] = T(0.5) * ((ub[c] + uin[c]) + dt * Lt[c]);
+                } else if (a.kind == RK3_MID) {
+#pragma unroll
+                    for (int c = 0; c < 4; c++)
+                        o[c] = (T(0.75) * ub[c] + T(0.25) * uin[c]) + T(0.25) * (dt * Lt[c]);
+                } else {
+                    const T third = T(1.0 / 3.0), two3 = T(2.0 / 3.0);
+#pragma unroll
+                    for (int c = 0; c < 4; c++) o[c] = (third * ub[c] + two3 * uin[c]) + two3 * (dt * Lt[c]);
+                }
+#pragma unroll
+                for (int c = 0; c < 4; c++) a.out[c][ij] = o[c];
+                if (a.want_smax) {
+                    T e, p, v[3], cs2;
+                    Counts cs;
+                    eos.prim(o, e, p, v, cs2, cs);
+                    smax = fmax(smax, max_speed(v, cs2));
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 4; c++) Fp[c] = Fn[c];
+            copy4(URt, URp);
+        }
+    }
+    flush_stats(a.stats, cnt, smax, a.mode == SW_FINAL && a.want_smax);
+}
+
+// ---------------------------------------------------------------------------
+// Standalone con2prim (Sec. 2.6) over n states.
+// ---------------------------------------------------------------------------
+template <typename T, class Eos>
+__global__ __launch_bounds__(256) void k_con2prim(C2PArgs<T> a, Eos eos)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    Counts cnt;
+    if (i < a.n) {
+        T u[4] = {a.U[0][i], a.U[1][i], a.U[2][i], a.U[3][i]};
+        T e, p, v[3], cs2;
+        Counts c1;
+        eos.prim(u, e, p, v, cs2, c1);
+        a.prim[0][i] = e; a.prim[1][i] = p;
+        a.prim[2][i] = v[0]; a.prim[3][i] = v[1]; a.prim[4][i] = v[2];
+        if (a.iters) a.iters[i] = (int32_t)c1.iters;
+        add_counts(cnt, c1);
+    }
+    flush_stats(a.stats, cnt, T(0), false);
+}
+
+// ---------------------------------------------------------------------------
+// Conservation sums: fixed assignment of cells to threads, fixed-order tree
+// in LDS, one partial per block; the final kernel sums the partials in order.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_totals_partial(TotalsArgs<T> a)
+{
+    __shared__ double sh[4][256];
+    const int t = threadIdx.x;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    const int64_t chunk = (a.n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = min(lo + chunk, a.n);
+    for (int64_t i = lo + t; i < hi; i += 256) {
+#pragma unroll
+        for (int c = 0; c < 4; c++) s[c] += (double)a.U[c][i];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; c++) sh[c][t] = s[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+#pragma unroll
+            for (int c = 0; c < 4; c++) sh[c][t] += sh[c][t + w];
+        }
+        __syncthreads();
+    }
+    if (t < 4) a.partial[(int64_t)blockIdx.x * 4 + t] = sh[t][0];
+}
+
+__global__ __launch_bounds__(256) void k_totals_final(const double* partial, int nblocks, double dV,
+                                                       double* out)
+{
+    __shared__ double sh[4][256];
+    const int t = threadIdx.x;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = t; b < nblocks; b += 256) {
+#pragma unroll
+        for (int c = 0; c < 4; c++) s[c] += partial[(int64_t)b * 4 + c];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; c++) sh[c][t] = s[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+#pragma unroll
+            for (int c = 0; c < 4; c++) sh[c][t] += sh[c][t + w];
+        }
+        __syncthreads();
+    }
+    if (t < 4) out[t] = sh[t][0] * dV;
+}
+
+__global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers
+// ---------------------------------------------------------------------------
+template <typename T, int D, int LIM, class Eos>
+static hipError_t launch_lim(bool jet, dim3 grid, dim3 block, hipStream_t s, const SweepArgs<T>& a,
+                             const Eos& eos)
+{
+    if constexpr (D == 2) {
+        if (jet) {
+            hipLaunchKernelGGL((k_sweep<T, D, LIM, Eos, true>), grid, block, 0, s, a, eos);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_sweep<T, D, LIM, Eos, false>), grid, block, 0, s, a, eos);
+    return hipGetLastError();
+}
+
+template <typename T, int D, class Eos>
+static hipError_t launch_axis(int lim, bool jet, dim3 grid, dim3 block, hipStream_t s,
+                              const SweepArgs<T>& a, const Eos& eos)
+{
+    switch (lim) {
+    case LIM_NONE: return launch_lim<T, D, LIM_NONE>(jet, grid, block, s, a, eos);
+    case LIM_MINMOD: return launch_lim<T, D, LIM_MINMOD>(jet, grid, block, s, a, eos);
+    case LIM_SUPERBEE: return launch_lim<T, D, LIM_SUPERBEE>(jet, grid, block, s, a, eos);
+    case LIM_MC: return launch_lim<T, D, LIM_MC>(jet, grid, block, s, a, eos);
+    case LIM_VANLEER: return launch_lim<T, D, LIM_VANLEER>(jet, grid, block, s, a, eos);
+    case LIM_VANALBADA: return launch_lim<T, D, LIM_VANALBADA>(jet, grid, block, s, a, eos);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_sweep(int axis, int lim, bool jet, dim3 grid, dim3 block, hipStream_t s,
+                        const SweepArgs<T>& a, const EosIdeal<T>& eos)
+{
+    switch (axis) {
+    case 0: return launch_axis<T, 0>(lim, false, grid, block, s, a, eos);
+    case 1: return launch_axis<T, 1>(lim, false, grid, block, s, a, eos);
+    case 2: return launch_axis<T, 2>(lim, jet, grid, block, s, a, eos);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_con2prim(int64_t n, hipStream_t s, const C2PArgs<T>& a, const EosIdeal<T>& eos)
+{
+    const int64_t nb = (n + 255) / 256;
+    hipLaunchKernelGGL((k_con2prim<T, EosIdeal<T>>), dim3((unsigned)nb), dim3(256), 0, s, a, eos);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_totals(hipStream_t s, const TotalsArgs<T>& a, int nblocks, double dV, double* out)
+{
+    hipLaunchKernelGGL((k_totals_partial<T>), dim3(nblocks), dim3(256), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(256), 0, s, a.partial, nblocks, dV, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(hipStream_t s, unsigned long long* p, int64_t n, unsigned long long v)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+template hipError_t launch_sweep<double>(int, int, bool, dim3, dim3, hipStream_t, const SweepArgs<double>&,
+                                         const EosIdeal<double>&);
+template hipError_t launch_sweep<float>(int, int, bool, dim3, dim3, hipStream_t, const SweepArgs<float>&,
+                                        const EosIdeal<float>&);
+template hipError_t launch_con2prim<double>(int64_t, hipStream_t, const C2PArgs<double>&,
+                                            const EosIdeal<double>&);
+template hipError_t launch_con2prim<float>(int64_t, hipStream_t, const C2PArgs<float>&,
+                                           const EosIdeal<float>&);
+template hipError_t launch_totals<double>(hipStream_t, const TotalsArgs<double>&, int, double, double*);
+template hipError_t launch_totals<float>(hipStream_t, const TotalsArgs<float>&, int, double, double*);
+
+}  // namespace mf

@@ -1,0 +1,88 @@
+// mf_params.hpp -- kernel argument blocks shared by the host runtime and the
+// kernels (plain structs passed by value as kernel arguments).
+#pragma once
+
+#include <stdint.h>
+
+namespace mf {
+
+// Scheme constants of one sweep axis d (lambda = dt / dx_d).
+template <typename T> struct AxisConst {
+    T lam;        // dt / dx_d            (MUSTA predictor)
+    T half_lam;   // dt / (2 dx_d)        (Hancock half step)
+    T half_alam;  // alpha dt / (2 dx_d)  (Lax-Wendroff half step)
+    T inv_2alam;  // dx_d / (2 alpha dt)  (Lax-Friedrichs viscosity)
+    T inv_dx;     // 1 / dx_d
+};
+
+// Slots of the per-event device statistics block (uint64 each).
+enum { ST_SMAX = 0, ST_FLOOR = 1, ST_BAD = 2, ST_ITERS = 3, ST_FALLBACK = 4, ST_WORDS = 8 };
+
+// Runge-Kutta combine of the last axis sweep (Sec. 2.3):
+//   RK_FIRST : out = u + dt L                                   (U1)
+//   RK2_LAST : out = 1/2 ((u0 + u) + dt L)                      (U^{n+1}, RK2)
+//   RK3_MID  : out = (3/4 u0 + 1/4 u) + 1/4 (dt L)              (U2, RK3)
+//   RK3_LAST : out = (1/3 u0 + 2/3 u) + 2/3 (dt L)              (U^{n+1}, RK3)
+enum { RK_FIRST = 0, RK2_LAST = 1, RK3_MID = 2, RK3_LAST = 3 };
+
+// Modes of an axis sweep.
+enum { SW_WRITE = 0, SW_ACCUM = 1, SW_FINAL = 2 };
+
+template <typename T> struct SweepArgs {
+    const T* u[4];      // stage input state (read with the stencil)
+    T* L[4];            // flux-divergence accumulator
+    const T* u0[4];     // Runge-Kutta base state U^n (SW_FINAL, kinds > RK_FIRST)
+    T* out[4];          // stage output (SW_FINAL)
+    int64_t nlines;     // lines along the sweep axis
+    int64_t stride_d;   // element stride along the sweep axis
+    int64_t stride_f;   // stride of the fast line axis
+    int64_t stride_s;   // stride of the slow line axis
+    int32_t N;          // cells along the sweep axis
+    int32_t n_fast;     // cells along the fast line axis
+    int32_t seg;        // cells per thread along the sweep axis
+    int32_t periodic;   // 1: periodic along the sweep axis, 0: outflow
+    int32_t k;          // MUSTA stages
+    int32_t mode;       // SW_*
+    int32_t kind;       // RK_* (SW_FINAL)
+    int32_t want_smax;  // SW_FINAL: reduce the max characteristic speed of out
+    int32_t axis_f;     // global axis of the fast line index
+    int32_t axis_s;     // global axis of the slow line index
+    AxisConst<T> ac;
+    T dt;
+    // moving point-jet source (SW_FINAL only)
+    double jet_pos[3];    // jet position at the stage time
+    double jet_ve;        // v dE/dx
+    double jet_v;         // v
+    double jet_norm;      // (2 pi sigma^2)^(-3/2)
+    double jet_inv2s2;    // 1 / (2 sigma^2)
+    double origin[3];
+    double dx[3];
+    unsigned long long* stats;  // ST_WORDS per event
+};
+
+template <typename T> struct C2PArgs {
+    const T* U[4];      // E, Mx, My, Mz
+    T* prim[5];         // e, p, vx, vy, vz
+    int32_t* iters;     // nullable
+    int64_t n;
+    unsigned long long* stats;
+};
+
+template <typename T> struct TotalsArgs {
+    const T* U[4];
+    int64_t n;
+    double* partial;    // 4 per block
+};
+
+// Monotone cubic table EoS (device pointers).
+struct TableArgs {
+    const double* e;    // nodes
+    const double* p;    // values
+    const double* m;    // node slopes
+    int32_t n;
+    int32_t log_uniform;  // nodes are log-uniform: index from log
+    double log_e0;        // ln e[0]
+    double inv_dlog;      // (n - 1) / (ln e[n-1] - ln e[0])
+};
+
+}  // namespace mf

@@ -1,0 +1,534 @@
+// mf_runtime.hip -- host runtime and C ABI (include/mf.h) of the MUSTA-FORCE
+// library: handles, library-owned scratch, the per-step launch sequence of
+// the dimensionally split Runge-Kutta stages, statistics and reductions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mf.h"
+#include "mf_kernels.hpp"
+
+using namespace mf;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define MF_HIP(call)                                                                           \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess) return fail(MF_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kTotalsBlocks = 512;
+
+struct Event {
+    mf_grid_desc d;
+    int64_t ncell = 0;
+    void* U[4] = {nullptr, nullptr, nullptr, nullptr};   // caller-owned
+    void* U1[4] = {nullptr, nullptr, nullptr, nullptr};  // RK stage 1 output
+    void* U2[4] = {nullptr, nullptr, nullptr, nullptr};  // RK3 stage 2 output
+    void* L[4] = {nullptr, nullptr, nullptr, nullptr};   // flux-divergence accumulator
+    double t = 0.0;
+    int64_t steps = 0;
+    bool jet = false;
+    double jet_x0[3] = {0, 0, 0};
+    double jet_v = 0, jet_dedx = 0, jet_sigma = 1;
+};
+
+size_t elem_size(int dtype) { return dtype == MF_F32 ? 4 : 8; }
+
+}  // namespace
+
+struct mf_grid_s {
+    std::vector<Event> ev;
+    hipStream_t stream = nullptr;
+    int eos_kind = -1;
+    double cs2 = 1.0 / 3.0;
+    int seg_override[3] = {0, 0, 0};
+    int block = 256;
+    unsigned long long* dstats = nullptr;  // (n_events + 1) * ST_WORDS; the last slot is scratch
+    double* dpartial = nullptr;            // kTotalsBlocks * 4
+    double* dtot = nullptr;                // n_events * 4
+    std::vector<void*> allocs;
+    // kernel timing (mf_set_profiling)
+    bool profiling = false;
+    struct Timed {
+        int axis;
+        hipEvent_t start, stop;
+    };
+    std::vector<Timed> timed;       // launches recorded since the last read
+    std::vector<hipEvent_t> pool;   // recycled events
+
+    ~mf_grid_s()
+    {
+        for (auto& t : timed) {
+            (void)hipEventDestroy(t.start);
+            (void)hipEventDestroy(t.stop);
+        }
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        for (void* p : allocs) (void)hipFree(p);
+    }
+    hipError_t take_event(hipEvent_t* e)
+    {
+        if (!pool.empty()) {
+            *e = pool.back();
+            pool.pop_back();
+            return hipSuccess;
+        }
+        return hipEventCreate(e);
+    }
+    int alloc(void** p, size_t bytes)
+    {
+        *p = nullptr;
+        if (bytes == 0) bytes = 8;
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) {
+            *p = nullptr;
+            (void)hipGetLastError();
+            return fail(MF_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                          hipGetErrorString(e));
+        }
+        allocs.push_back(*p);
+        return MF_OK;
+    }
+};
+
+namespace {
+
+// Sweep geometry of axis d on an (nx, ny, nz) grid with x fastest.
+struct AxisGeom {
+    int N, n_fast, axis_f, axis_s;
+    int64_t nlines, stride_d, stride_f, stride_s;
+};
+
+AxisGeom axis_geom(const int32_t n[3], int d)
+{
+    const int64_t nx = n[0], ny = n[1], nz = n[2];
+    AxisGeom g;
+    if (d == 0) {
+        g = {n[0], n[1], 1, 2, ny * nz, 1, nx, nx * ny};
+    } else if (d == 1) {
+        g = {n[1], n[0], 0, 2, nx * nz, nx, 1, nx * ny};
+    } else {
+        g = {n[2], n[0], 0, 1, nx * ny, nx * ny, 1, nx};
+    }
+    return g;
+}
+
+// Cells per thread along the sweep axis: enough segments to put about three
+// wavefronts on every SIMD of the 256 compute units, but at least 16 cells
+// per segment (each segment recomputes two reconstructions and one interface).
+int auto_seg(const AxisGeom& g)
+{
+    const int64_t target_threads = 256LL * 4 * 64 * 3;
+    int64_t nseg = (target_threads + g.nlines - 1) / g.nlines;
+    nseg = std::max<int64_t>(1, std::min<int64_t>(nseg, (g.N + 15) / 16));
+    return (int)((g.N + nseg - 1) / nseg);
+}
+
+template <typename T>
+void set_axis_const(AxisConst<T>& ac, double dt, double dx, double alpha)
+{
+    const double lam = dt / dx;
+    ac.lam = (T)lam;
+    ac.half_lam = (T)(0.5 * lam);
+    ac.half_alam = (T)(0.5 * alpha * lam);
+    ac.inv_2alam = (T)(1.0 / (2.0 * alpha * lam));
+    ac.inv_dx = (T)(1.0 / dx);
+}
+
+template <typename T>
+int run_stage(mf_grid_s* g, Event& ev, unsigned long long* stats, void* const uin[4], void* const u0[4],
+              void* const out[4], int kind, double dt, double ts, bool want_smax)
+{
+    EosIdeal<T> eos;
+    eos.c = (T)g->cs2;
+    eos.q = (T)(1.0 + g->cs2);
+    eos.q2 = (T)((1.0 + g->cs2) * (1.0 + g->cs2));
+    eos.c4 = (T)(4.0 * g->cs2);
+    for (int d = 0; d < 3; d++) {
+        const AxisGeom geo = axis_geom(ev.d.n, d);
+        SweepArgs<T> a;
+        std::memset(&a, 0, sizeof(a));
+        for (int c = 0; c < 4; c++) {
+            a.u[c] = (const T*)uin[c];
+            a.L[c] = (T*)ev.L[c];
+            a.u0[c] = (const T*)u0[c];
+            a.out[c] = (T*)out[c];
+        }
+        a.nlines = geo.nlines;
+        a.stride_d = geo.stride_d;
+        a.stride_f = geo.stride_f;
+        a.stride_s = geo.stride_s;
+        a.N = geo.N;
+        a.n_fast = geo.n_fast;
+        a.seg = g->seg_override[d] > 0 ? std::min(g->seg_override[d], geo.N) : auto_seg(geo);
+        a.periodic = ev.d.bc[d] == MF_BC_PERIODIC;
+        a.k = ev.d.musta_k;
+        a.mode = d == 0 ? SW_WRITE : (d == 1 ? SW_ACCUM : SW_FINAL);
+        a.kind = kind;
+        a.want_smax = want_smax ? 1 : 0;
+        a.axis_f = geo.axis_f;
+        a.axis_s = geo.axis_s;
+        set_axis_const(a.ac, dt, ev.d.dx[d], ev.d.alpha);
+        a.dt = (T)dt;
+        const bool jet = ev.jet && d == 2;
+        if (jet) {
+            a.jet_pos[0] = ev.jet_x0[0] + ev.jet_v * ts;
+            a.jet_pos[1] = ev.jet_x0[1];
+            a.jet_pos[2] = ev.jet_x0[2];
+            a.jet_ve = ev.jet_v * ev.jet_dedx;
+            a.jet_v = ev.jet_v;
+            a.jet_norm = std::pow(2.0 * M_PI * ev.jet_sigma * ev.jet_sigma, -1.5);
+            a.jet_inv2s2 = 1.0 / (2.0 * ev.jet_sigma * ev.jet_sigma);
+        }
+        for (int q = 0; q < 3; q++) {
+            a.origin[q] = ev.d.origin[q];
+            a.dx[q] = ev.d.dx[q];
+        }
+        a.stats = stats;
+        const int64_t nseg = (geo.N + a.seg - 1) / a.seg;
+        dim3 block(g->block);
+        dim3 grid((unsigned)((geo.nlines + g->block - 1) / g->block), (unsigned)nseg);
+        mf_grid_s::Timed tm{d, nullptr, nullptr};
+        if (g->profiling) {
+            MF_HIP(g->take_event(&tm.start));
+            MF_HIP(g->take_event(&tm.stop));
+            MF_HIP(hipEventRecord(tm.start, g->stream));
+        }
+        hipError_t e = launch_sweep<T>(d, ev.d.limiter, jet, grid, block, g->stream, a, eos);
+        if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("sweep launch: ") + hipGetErrorString(e));
+        if (g->profiling) {
+            MF_HIP(hipEventRecord(tm.stop, g->stream));
+            g->timed.push_back(tm);
+        }
+    }
+    return MF_OK;
+}
+
+template <typename T>
+int run_steps(mf_grid_s* g, Event& ev, unsigned long long* stats, double dt, int nsteps)
+{
+    int rc;
+    for (int s = 0; s < nsteps; s++) {
+        const double t = ev.t;
+        if (ev.d.rk_order == 3) {
+            if ((rc = run_stage<T>(g, ev, stats, ev.U, ev.U, ev.U1, RK_FIRST, dt, t, false))) return rc;
+            if ((rc = run_stage<T>(g, ev, stats, ev.U1, ev.U, ev.U2, RK3_MID, dt, t + dt, false))) return rc;
+            if ((rc = run_stage<T>(g, ev, stats, ev.U2, ev.U, ev.U, RK3_LAST, dt, t + 0.5 * dt, true))) return rc;
+        } else {
+            if ((rc = run_stage<T>(g, ev, stats, ev.U, ev.U, ev.U1, RK_FIRST, dt, t, false))) return rc;
+            if ((rc = run_stage<T>(g, ev, stats, ev.U1, ev.U, ev.U, RK2_LAST, dt, t + dt, true))) return rc;
+        }
+        ev.steps++;
+        ev.t = ev.t + dt;
+    }
+    return MF_OK;
+}
+
+template <typename T>
+int enqueue_totals(mf_grid_s* g, const Event& ev, double* out)
+{
+    TotalsArgs<T> a;
+    for (int c = 0; c < 4; c++) a.U[c] = (const T*)ev.U[c];
+    a.n = ev.ncell;
+    a.partial = g->dpartial;
+    const double dV = ev.d.dx[0] * ev.d.dx[1] * ev.d.dx[2];
+    hipError_t e = launch_totals<T>(g->stream, a, kTotalsBlocks, dV, out);
+    if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("totals launch: ") + hipGetErrorString(e));
+    return MF_OK;
+}
+
+int check_desc(const mf_grid_desc& d)
+{
+    for (int q = 0; q < 3; q++) {
+        if (d.n[q] < 1) return fail(MF_ERR_ARG, "grid size n[" + std::to_string(q) + "] must be >= 1");
+        if (!(d.dx[q] > 0.0) || !std::isfinite(d.dx[q])) return fail(MF_ERR_ARG, "dx must be finite and > 0");
+        if (d.bc[q] != MF_BC_OUTFLOW && d.bc[q] != MF_BC_PERIODIC) return fail(MF_ERR_ARG, "unknown boundary code");
+        if (!std::isfinite(d.origin[q])) return fail(MF_ERR_ARG, "origin must be finite");
+    }
+    if ((int64_t)d.n[0] * d.n[1] > INT32_MAX || (int64_t)d.n[0] * d.n[1] * d.n[2] > (int64_t)1 << 40)
+        return fail(MF_ERR_ARG, "grid too large");
+    if (d.dtype != MF_F64 && d.dtype != MF_F32) return fail(MF_ERR_ARG, "unknown dtype");
+    if (d.limiter < MF_LIM_NONE || d.limiter > MF_LIM_VANALBADA) return fail(MF_ERR_ARG, "unknown limiter");
+    if (d.musta_k < 1 || d.musta_k > 64) return fail(MF_ERR_ARG, "musta_k must be in [1, 64]");
+    if (d.rk_order != 2 && d.rk_order != 3) return fail(MF_ERR_ARG, "rk_order must be 2 or 3");
+    if (!(d.alpha > 0.0) || !std::isfinite(d.alpha)) return fail(MF_ERR_ARG, "alpha must be finite and > 0");
+    return MF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mf_last_error(void) { return g_err.c_str(); }
+
+int mf_grid_init(mf_grid_t* out, const mf_grid_desc* descs, int32_t n_events, void* const* U_dev, void* stream)
+{
+    g_err.clear();
+    if (!out || !descs || !U_dev) return fail(MF_ERR_ARG, "null argument");
+    *out = nullptr;
+    if (n_events < 1) return fail(MF_ERR_ARG, "n_events must be >= 1");
+    for (int i = 0; i < n_events; i++) {
+        int rc = check_desc(descs[i]);
+        if (rc) return rc;
+        for (int c = 0; c < 4; c++)
+            if (!U_dev[4 * i + c]) return fail(MF_ERR_ARG, "null state pointer");
+    }
+    mf_grid_s* g = new (std::nothrow) mf_grid_s();
+    if (!g) return fail(MF_ERR_NOMEM, "host allocation failed");
+    g->stream = (hipStream_t)stream;
+    g->ev.resize(n_events);
+    int rc = MF_OK;
+    for (int i = 0; i < n_events && rc == MF_OK; i++) {
+        Event& ev = g->ev[i];
+        ev.d = descs[i];
+        ev.ncell = (int64_t)ev.d.n[0] * ev.d.n[1] * ev.d.n[2];
+        const size_t bytes = (size_t)ev.ncell * elem_size(ev.d.dtype);
+        for (int c = 0; c < 4 && rc == MF_OK; c++) {
+            ev.U[c] = U_dev[4 * i + c];
+            rc = g->alloc(&ev.U1[c], bytes);
+            if (rc == MF_OK) rc = g->alloc(&ev.L[c], bytes);
+            if (rc == MF_OK && ev.d.rk_order == 3) rc = g->alloc(&ev.U2[c], bytes);
+        }
+    }
+    if (rc == MF_OK) rc = g->alloc((void**)&g->dstats, sizeof(unsigned long long) * ST_WORDS * (n_events + 1));
+    if (rc == MF_OK) rc = g->alloc((void**)&g->dpartial, sizeof(double) * 4 * kTotalsBlocks);
+    if (rc == MF_OK) rc = g->alloc((void**)&g->dtot, sizeof(double) * 4 * n_events);
+    if (rc != MF_OK) {
+        std::string msg = g_err;
+        delete g;
+        return fail(rc, msg);
+    }
+    *out = g;
+    return MF_OK;
+}
+
+int mf_grid_free(mf_grid_t g)
+{
+    if (!g) return fail(MF_ERR_ARG, "null handle");
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    else (void)hipDeviceSynchronize();
+    delete g;
+    return MF_OK;
+}
+
+int mf_set_eos(mf_grid_t g, int32_t kind, double cs2, const double* e_tab, const double* p_tab, int32_t n_tab,
+               const mf_surrogate* s)
+{
+    (void)e_tab; (void)p_tab; (void)n_tab;
+    if (!g) return fail(MF_ERR_ARG, "null handle");
+    if (kind == MF_EOS_IDEAL) {
+        if (!(cs2 > 0.0 && cs2 < 1.0)) return fail(MF_ERR_ARG, "cs2 must be in (0, 1)");
+        if (s) return fail(MF_ERR_ARG, "a surrogate needs the table EoS");
+        g->eos_kind = MF_EOS_IDEAL;
+        g->cs2 = cs2;
+        return MF_OK;
+    }
+    if (kind == MF_EOS_TABLE) return fail(MF_ERR_ARG, "table EoS not available in this build");
+    return fail(MF_ERR_ARG, "unknown EoS kind");
+}
+
+int mf_set_source_jet(mf_grid_t g, int32_t event, const double x0[3], double v, double dEdx, double sigma)
+{
+    if (!g || !x0) return fail(MF_ERR_ARG, "null argument");
+    if (event < 0 || event >= (int)g->ev.size()) return fail(MF_ERR_ARG, "event out of range");
+    if (!(v > 0.0 && v < 1.0) || !(sigma > 0.0) || !std::isfinite(dEdx))
+        return fail(MF_ERR_ARG, "jet needs 0 < v < 1, sigma > 0, finite dEdx");
+    Event& ev = g->ev[event];
+    ev.jet = dEdx != 0.0;
+    for (int q = 0; q < 3; q++) ev.jet_x0[q] = x0[q];
+    ev.jet_v = v;
+    ev.jet_dedx = dEdx;
+    ev.jet_sigma = sigma;
+    return MF_OK;
+}
+
+int mf_set_time(mf_grid_t g, int32_t event, double t, int64_t steps)
+{
+    if (!g) return fail(MF_ERR_ARG, "null handle");
+    if (event < 0 || event >= (int)g->ev.size()) return fail(MF_ERR_ARG, "event out of range");
+    if (!std::isfinite(t) || steps < 0) return fail(MF_ERR_ARG, "bad time");
+    g->ev[event].t = t;
+    g->ev[event].steps = steps;
+    return MF_OK;
+}
+
+int mf_set_profiling(mf_grid_t g, int32_t enable)
+{
+    if (!g) return fail(MF_ERR_ARG, "null handle");
+    g->profiling = enable != 0;
+    return MF_OK;
+}
+
+int mf_get_profile(mf_grid_t g, double ms[3], int64_t launches[3])
+{
+    if (!g || !ms || !launches) return fail(MF_ERR_ARG, "null argument");
+    MF_HIP(hipStreamSynchronize(g->stream));
+    for (int q = 0; q < 3; q++) {
+        ms[q] = 0.0;
+        launches[q] = 0;
+    }
+    for (auto& t : g->timed) {
+        float dt = 0.0f;
+        MF_HIP(hipEventElapsedTime(&dt, t.start, t.stop));
+        ms[t.axis] += dt;
+        launches[t.axis]++;
+        g->pool.push_back(t.start);
+        g->pool.push_back(t.stop);
+    }
+    g->timed.clear();
+    return MF_OK;
+}
+
+int mf_set_tuning(mf_grid_t g, const int32_t seg[3], int32_t block)
+{
+    if (!g) return fail(MF_ERR_ARG, "null handle");
+    if (block != 64 && block != 128 && block != 256) return fail(MF_ERR_ARG, "block must be 64, 128 or 256");
+    for (int q = 0; q < 3; q++) {
+        if (seg && seg[q] < 0) return fail(MF_ERR_ARG, "seg must be >= 0");
+        g->seg_override[q] = seg ? seg[q] : 0;
+    }
+    g->block = block;
+    return MF_OK;
+}
+
+static int collect_stats(mf_grid_t g, double dt, mf_stats* st)
+{
+    const int ne = (int)g->ev.size();
+    for (int i = 0; i < ne; i++) {
+        int rc = g->ev[i].d.dtype == MF_F32 ? enqueue_totals<float>(g, g->ev[i], g->dtot + 4 * i)
+                                            : enqueue_totals<double>(g, g->ev[i], g->dtot + 4 * i);
+        if (rc) return rc;
+    }
+    std::vector<unsigned long long> hs((size_t)ST_WORDS * ne);
+    std::vector<double> ht((size_t)4 * ne);
+    MF_HIP(hipMemcpyAsync(hs.data(), g->dstats, hs.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                          g->stream));
+    MF_HIP(hipMemcpyAsync(ht.data(), g->dtot, ht.size() * sizeof(double), hipMemcpyDeviceToHost, g->stream));
+    MF_HIP(hipStreamSynchronize(g->stream));
+    for (int i = 0; i < ne; i++) {
+        const Event& ev = g->ev[i];
+        mf_stats& s = st[i];
+        std::memset(&s, 0, sizeof(s));
+        const unsigned long long* w = &hs[(size_t)ST_WORDS * i];
+        double smax;
+        std::memcpy(&smax, &w[ST_SMAX], sizeof(double));
+        s.t = ev.t;
+        s.steps = ev.steps;
+        s.smax = smax;
+        const double dxmin = std::min(ev.d.dx[0], std::min(ev.d.dx[1], ev.d.dx[2]));
+        s.courant = smax * dt / dxmin;
+        for (int c = 0; c < 4; c++) s.totals[c] = ht[4 * i + c];
+        s.n_floor = (int64_t)w[ST_FLOOR];
+        s.n_bad = (int64_t)w[ST_BAD];
+        s.newton_iters = (int64_t)w[ST_ITERS];
+        s.n_fallback = (int64_t)w[ST_FALLBACK];
+    }
+    return MF_OK;
+}
+
+int mf_step(mf_grid_t g, double dt, int32_t nsteps, mf_stats* st)
+{
+    if (!g) return fail(MF_ERR_ARG, "null handle");
+    if (g->eos_kind < 0) return fail(MF_ERR_STATE, "no equation of state set");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(MF_ERR_ARG, "dt must be finite and > 0");
+    if (nsteps < 0) return fail(MF_ERR_ARG, "nsteps must be >= 0");
+    const int ne = (int)g->ev.size();
+    hipError_t e = launch_fill_u64(g->stream, g->dstats, (int64_t)ST_WORDS * ne, 0ULL);
+    if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("stats reset: ") + hipGetErrorString(e));
+    for (int i = 0; i < ne; i++) {
+        Event& ev = g->ev[i];
+        unsigned long long* stats = g->dstats + (size_t)ST_WORDS * i;
+        int rc = ev.d.dtype == MF_F32 ? run_steps<float>(g, ev, stats, dt, nsteps)
+                                      : run_steps<double>(g, ev, stats, dt, nsteps);
+        if (rc) return rc;
+    }
+    bool strict = false;
+    for (const Event& ev : g->ev) strict = strict || (ev.d.flags & MF_FLAG_STRICT);
+    if (!st && !strict) return MF_OK;
+    std::vector<mf_stats> local;
+    if (!st) {
+        local.resize(ne);
+        st = local.data();
+    }
+    int rc = collect_stats(g, dt, st);
+    if (rc) return rc;
+    for (int i = 0; i < ne; i++) {
+        if (!(g->ev[i].d.flags & MF_FLAG_STRICT)) continue;
+        if (st[i].n_bad > 0 || st[i].n_floor > 0)
+            return fail(MF_ERR_UNPHYSICAL, "event " + std::to_string(i) + ": unphysical states met (" +
+                                               std::to_string(st[i].n_bad) + " bad, " + std::to_string(st[i].n_floor) +
+                                               " clamped)");
+        if (g->ev[i].d.alpha * st[i].courant > 1.0)
+            return fail(MF_ERR_CFL, "event " + std::to_string(i) + ": alpha * Courant number exceeds 1");
+    }
+    return MF_OK;
+}
+
+int mf_batch_step(mf_grid_t g, const double* dt, int32_t nsteps, mf_stats* st)
+{
+    (void)g; (void)dt; (void)nsteps; (void)st;
+    return fail(MF_ERR_STATE, "batched stepping not available in this build");
+}
+
+int mf_con2prim(mf_grid_t g, const void* const U[4], void* const prim[5], int64_t n, int32_t* iters_dev,
+                int32_t mode)
+{
+    if (!g || !U || !prim) return fail(MF_ERR_ARG, "null argument");
+    if (g->eos_kind < 0) return fail(MF_ERR_STATE, "no equation of state set");
+    if (n < 0) return fail(MF_ERR_ARG, "n must be >= 0");
+    if (mode != MF_C2P_PLAIN) return fail(MF_ERR_ARG, "seeded con2prim needs a surrogate");
+    if (n == 0) return MF_OK;
+    for (int c = 0; c < 4; c++)
+        if (!U[c]) return fail(MF_ERR_ARG, "null state pointer");
+    for (int c = 0; c < 5; c++)
+        if (!prim[c]) return fail(MF_ERR_ARG, "null output pointer");
+    unsigned long long* stats = g->dstats + (size_t)ST_WORDS * g->ev.size();
+    hipError_t e;
+    if (g->ev[0].d.dtype == MF_F32) {
+        C2PArgs<float> a;
+        for (int c = 0; c < 4; c++) a.U[c] = (const float*)U[c];
+        for (int c = 0; c < 5; c++) a.prim[c] = (float*)prim[c];
+        a.iters = iters_dev; a.n = n; a.stats = stats;
+        EosIdeal<float> eos{(float)g->cs2, (float)(1.0 + g->cs2), (float)((1.0 + g->cs2) * (1.0 + g->cs2)),
+                            (float)(4.0 * g->cs2)};
+        e = launch_con2prim<float>(n, g->stream, a, eos);
+    } else {
+        C2PArgs<double> a;
+        for (int c = 0; c < 4; c++) a.U[c] = (const double*)U[c];
+        for (int c = 0; c < 5; c++) a.prim[c] = (double*)prim[c];
+        a.iters = iters_dev; a.n = n; a.stats = stats;
+        EosIdeal<double> eos{g->cs2, 1.0 + g->cs2, (1.0 + g->cs2) * (1.0 + g->cs2), 4.0 * g->cs2};
+        e = launch_con2prim<double>(n, g->stream, a, eos);
+    }
+    if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("con2prim launch: ") + hipGetErrorString(e));
+    return MF_OK;
+}
+
+int mf_totals(mf_grid_t g, int32_t event, double out[4])
+{
+    if (!g || !out) return fail(MF_ERR_ARG, "null argument");
+    if (event < 0 || event >= (int)g->ev.size()) return fail(MF_ERR_ARG, "event out of range");
+    const Event& ev = g->ev[event];
+    int rc = ev.d.dtype == MF_F32 ? enqueue_totals<float>(g, ev, g->dtot + 4 * event)
+                                  : enqueue_totals<double>(g, ev, g->dtot + 4 * event);
+    if (rc) return rc;
+    MF_HIP(hipMemcpyAsync(out, g->dtot + 4 * event, 4 * sizeof(double), hipMemcpyDeviceToHost, g->stream));
+    MF_HIP(hipStreamSynchronize(g->stream));
+    return MF_OK;
+}
+
+}  // extern "C"

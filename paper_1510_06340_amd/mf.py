@@ -1,0 +1,229 @@
+"""Thin ctypes binding of libmf.so (the C ABI declared in include/mf.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  PyTorch supplies device memory and the stream; state tensors are
+passed by raw pointer and must stay alive (the Grid keeps references).
+There is no fallback: if libmf.so is missing or the device is unavailable,
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmf.so")
+
+MF_OK, MF_ERR_ARG, MF_ERR_NOMEM, MF_ERR_HIP, MF_ERR_STATE, MF_ERR_UNPHYSICAL, MF_ERR_CFL = 0, -1, -2, -3, -4, -5, -6
+MF_BC_OUTFLOW, MF_BC_PERIODIC = 0, 1
+MF_F64, MF_F32 = 0, 1
+MF_LIM_NONE, MF_LIM_MINMOD, MF_LIM_SUPERBEE, MF_LIM_MC, MF_LIM_VANLEER, MF_LIM_VANALBADA = range(6)
+MF_EOS_IDEAL, MF_EOS_TABLE = 0, 1
+MF_C2P_PLAIN, MF_C2P_SEEDED = 0, 1
+MF_FLAG_STRICT = 1
+
+EXPORTS = ["mf_grid_init", "mf_set_eos", "mf_set_source_jet", "mf_set_time", "mf_step", "mf_batch_step",
+           "mf_con2prim", "mf_totals", "mf_set_tuning", "mf_set_profiling", "mf_get_profile", "mf_grid_free",
+           "mf_last_error"]
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("dx", C.c_double * 3), ("origin", C.c_double * 3), ("bc", C.c_int32 * 3),
+                ("dtype", C.c_int32), ("limiter", C.c_int32), ("musta_k", C.c_int32), ("rk_order", C.c_int32),
+                ("alpha", C.c_double), ("flags", C.c_uint32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("t", C.c_double), ("steps", C.c_int64), ("smax", C.c_double), ("courant", C.c_double),
+                ("totals", C.c_double * 4), ("n_floor", C.c_int64), ("n_bad", C.c_int64),
+                ("newton_iters", C.c_int64), ("n_fallback", C.c_int64)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["totals"] = list(self.totals)
+        return d
+
+
+class Surrogate(C.Structure):
+    _fields_ = [("hidden", C.c_int32), ("w1", C.POINTER(C.c_float)), ("b1", C.POINTER(C.c_float)),
+                ("w2", C.POINTER(C.c_float)), ("b2", C.POINTER(C.c_float)), ("w3", C.POINTER(C.c_float)),
+                ("b3", C.c_float), ("in_shift", C.c_float * 2), ("in_scale", C.c_float * 2),
+                ("out_shift", C.c_float), ("out_scale", C.c_float), ("max_newton", C.c_int32)]
+
+
+class MFError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mf error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libmf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1510_06340_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.mf_last_error.restype = C.c_char_p
+        L.mf_grid_init.argtypes = [C.POINTER(vp), C.POINTER(GridDesc), C.c_int32, C.POINTER(vp), vp]
+        L.mf_set_eos.argtypes = [vp, C.c_int32, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                 C.c_int32, C.POINTER(Surrogate)]
+        L.mf_set_source_jet.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.c_double, C.c_double, C.c_double]
+        L.mf_set_time.argtypes = [vp, C.c_int32, C.c_double, C.c_int64]
+        L.mf_step.argtypes = [vp, C.c_double, C.c_int32, C.POINTER(Stats)]
+        L.mf_batch_step.argtypes = [vp, C.POINTER(C.c_double), C.c_int32, C.POINTER(Stats)]
+        L.mf_con2prim.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.c_int64, vp, C.c_int32]
+        L.mf_totals.argtypes = [vp, C.c_int32, C.POINTER(C.c_double)]
+        L.mf_set_tuning.argtypes = [vp, C.POINTER(C.c_int32), C.c_int32]
+        L.mf_set_profiling.argtypes = [vp, C.c_int32]
+        L.mf_get_profile.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.mf_grid_free.argtypes = [vp]
+        for name in EXPORTS:
+            if name != "mf_last_error":
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().mf_last_error().decode()
+
+
+def _check(rc):
+    if rc != MF_OK:
+        raise MFError(rc, last_error())
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+def make_desc(n, dx, origin, bc, dtype=MF_F64, limiter=MF_LIM_MC, k=3, rk=2, alpha=3.0, flags=0) -> GridDesc:
+    d = GridDesc()
+    d.n[:] = [int(v) for v in n]
+    d.dx[:] = [float(v) for v in dx]
+    d.origin[:] = [float(v) for v in origin]
+    d.bc[:] = [int(v) for v in bc]
+    d.dtype, d.limiter, d.musta_k, d.rk_order = int(dtype), int(limiter), int(k), int(rk)
+    d.alpha, d.flags = float(alpha), int(flags)
+    return d
+
+
+def desc_from_workload(w, dtype=MF_F64, flags=0) -> GridDesc:
+    return make_desc(w.n, w.dx, w.xlo, w.bc, dtype, w.limiter, w.k, w.rk, w.alpha, flags)
+
+
+class Grid:
+    """A handle over one or more events whose state lives in caller-owned device tensors.
+
+    states: list (one per event) of 4 contiguous CUDA tensors (E, Mx, My, Mz),
+    each with n[0]*n[1]*n[2] elements of the event's dtype.
+    """
+
+    def __init__(self, descs, states, stream=None):
+        import torch
+        if isinstance(descs, GridDesc):
+            descs = [descs]
+        if len(descs) != len(states):
+            raise ValueError("one state (4 tensors) per descriptor")
+        self._torch = torch
+        self.descs = list(descs)
+        self.states = [list(s) for s in states]
+        for d, s in zip(self.descs, self.states):
+            want = torch.float32 if d.dtype == MF_F32 else torch.float64
+            ncell = d.n[0] * d.n[1] * d.n[2]
+            if len(s) != 4:
+                raise ValueError("4 component tensors per event")
+            for t in s:
+                if not t.is_cuda or t.dtype != want or not t.is_contiguous() or t.numel() != ncell:
+                    raise ValueError("state tensors must be contiguous CUDA tensors of the event's dtype and size")
+        arr = (C.c_void_p * (4 * len(self.descs)))(*[_ptr(t) for s in self.states for t in s])
+        darr = (GridDesc * len(self.descs))(*self.descs)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = C.c_void_p()
+        _check(lib().mf_grid_init(C.byref(h), darr, len(self.descs), arr, C.c_void_p(stream.cuda_stream)))
+        self.h = h
+
+    @property
+    def n_events(self):
+        return len(self.descs)
+
+    def set_eos_ideal(self, cs2=1.0 / 3.0):
+        _check(lib().mf_set_eos(self.h, MF_EOS_IDEAL, float(cs2), None, None, 0, None))
+
+    def set_eos_table(self, e, p, surrogate: Surrogate | None = None):
+        import numpy as np
+        e = np.ascontiguousarray(e, dtype=np.float64)
+        p = np.ascontiguousarray(p, dtype=np.float64)
+        D = C.POINTER(C.c_double)
+        _check(lib().mf_set_eos(self.h, MF_EOS_TABLE, 0.0, e.ctypes.data_as(D), p.ctypes.data_as(D), len(e),
+                                C.byref(surrogate) if surrogate is not None else None))
+
+    def set_jet(self, event, x0, v, dedx, sigma):
+        x = (C.c_double * 3)(*[float(q) for q in x0])
+        _check(lib().mf_set_source_jet(self.h, int(event), x, float(v), float(dedx), float(sigma)))
+
+    def set_time(self, event, t, steps=0):
+        _check(lib().mf_set_time(self.h, int(event), float(t), int(steps)))
+
+    def set_tuning(self, seg=(0, 0, 0), block=256):
+        s = (C.c_int32 * 3)(*[int(q) for q in seg])
+        _check(lib().mf_set_tuning(self.h, s, int(block)))
+
+    def step(self, dt, nsteps, stats=True):
+        """Advance every event; returns a list of per-event stats dicts (or None)."""
+        if stats:
+            st = (Stats * self.n_events)()
+            _check(lib().mf_step(self.h, float(dt), int(nsteps), st))
+            return [s.as_dict() for s in st]
+        _check(lib().mf_step(self.h, float(dt), int(nsteps), None))
+        return None
+
+    def batch_step(self, dts, nsteps, stats=True):
+        dt = (C.c_double * self.n_events)(*[float(v) for v in dts])
+        if stats:
+            st = (Stats * self.n_events)()
+            _check(lib().mf_batch_step(self.h, dt, int(nsteps), st))
+            return [s.as_dict() for s in st]
+        _check(lib().mf_batch_step(self.h, dt, int(nsteps), None))
+        return None
+
+    def con2prim(self, U, prim, iters=None, mode=MF_C2P_PLAIN):
+        """U: 4 device tensors, prim: 5 device tensors (e, p, vx, vy, vz), iters: int32 tensor or None."""
+        n = U[0].numel()
+        u = (C.c_void_p * 4)(*[_ptr(t) for t in U])
+        p = (C.c_void_p * 5)(*[_ptr(t) for t in prim])
+        it = C.c_void_p(_ptr(iters)) if iters is not None else None
+        _check(lib().mf_con2prim(self.h, u, p, n, it, int(mode)))
+
+    def set_profiling(self, enable=True):
+        _check(lib().mf_set_profiling(self.h, 1 if enable else 0))
+
+    def get_profile(self):
+        """Per sweep axis (x, y, z): (summed kernel ms, launches) since the last read."""
+        ms = (C.c_double * 3)()
+        n = (C.c_int64 * 3)()
+        _check(lib().mf_get_profile(self.h, ms, n))
+        return list(ms), list(n)
+
+    def totals(self, event=0):
+        out = (C.c_double * 4)()
+        _check(lib().mf_totals(self.h, int(event), out))
+        return list(out)
+
+    def free(self):
+        if getattr(self, "h", None):
+            _check(lib().mf_grid_free(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
