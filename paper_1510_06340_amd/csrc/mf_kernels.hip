@@ -92,40 +92,43 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a, Eos eos)
             return base + (int64_t)jj * sd;
         };
 
+        // The march starts two cells early: iteration j reconstructs cell j+1
+        // and (from j = s0-1 on) solves interface j+1/2; cells are written
+        // from j = s0 on.  Warm-up and body share one instance of the code,
+        // so results do not depend on the segmentation.
         T w0[4], w1[4], w2[4];
         T ULt[4], URt[4], URp[4], Fp[4], Fn[4];
-        load4(a.u, cell(s0 - 2), w0);
-        load4(a.u, cell(s0 - 1), w1);
-        load4(a.u, cell(s0), w2);
-        {   // cell s0 - 1 and interface s0 - 1/2 (owned by the segment only at the line start)
-            Counts c1;
-            hancock<D, LIM>(w0, w1, w2, a.ac.half_lam, ULt, URp, eos, c1);
-            copy4(w1, w0);
-            copy4(w2, w1);
-            load4(a.u, cell(s0 + 1), w2);
-            hancock<D, LIM>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, cnt);  // cell s0
-            musta<D>(URp, ULt, a.k, a.ac, Fp, eos, c1);
-            if (s0 == 0) add_counts(cnt, c1);
-            copy4(URt, URp);
-        }
-
-        for (int j = s0; j < s1; j++) {
+        load4(a.u, cell(s0 - 2), w1);
+        load4(a.u, cell(s0 - 1), w2);
+        for (int j = s0 - 2; j < s1; j++) {
             copy4(w1, w0);
             copy4(w2, w1);
             load4(a.u, cell(j + 2), w2);
             const int64_t ij = base + (int64_t)j * sd;
+            const bool body = j >= s0;
             T Lp[4], ub[4];
-            if (a.mode != SW_WRITE) load4((const T* const*)a.L, ij, Lp);
-            if (a.mode == SW_FINAL && a.kind != RK_FIRST) load4(a.u0, ij, ub);
+            if (body && a.mode != SW_WRITE) load4((const T* const*)a.L, ij, Lp);
+            if (body && a.mode == SW_FINAL && a.kind != RK_FIRST) load4(a.u0, ij, ub);
 
-            // cell j+1: owned unless it is the next segment's first cell
-            if (j + 1 < s1 || j + 1 == N) {
-                hancock<D, LIM>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, cnt);
-            } else {
-                Counts c2;
-                hancock<D, LIM>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, c2);
+            // cell j+1; counted once over all segments of the line (cells -1..N)
+            Counts ch;
+            hancock<D, LIM>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, ch);
+            const int c1 = j + 1;
+            if (c1 == s0 - 1 ? s0 == 0 : (c1 < s1 || c1 == N)) add_counts(cnt, ch);
+            if (j == s0 - 2) {
+                copy4(URt, URp);
+                continue;
             }
-            musta<D>(URp, ULt, a.k, a.ac, Fn, eos, cnt);  // interface j + 1/2
+            // interface j + 1/2; counted once over all segments (interfaces -1/2..N-1/2)
+            Counts cm;
+            musta<D>(URp, ULt, a.k, a.ac, Fn, eos, cm);
+            if (body || s0 == 0) add_counts(cnt, cm);
+            copy4(URt, URp);
+            if (!body) {
+#pragma unroll
+                for (int c = 0; c < 4; c++) Fp[c] = Fn[c];
+                continue;
+            }
 
             T Ld[4];
 #pragma unroll
@@ -183,7 +186,6 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a, Eos eos)
             }
 #pragma unroll
             for (int c = 0; c < 4; c++) Fp[c] = Fn[c];
-            copy4(URt, URp);
         }
     }
     flush_stats(a.stats, cnt, smax, a.mode == SW_FINAL && a.want_smax);
