@@ -161,8 +161,9 @@ int mf_con2prim(mf_grid_t g, const void* const U[4], void* const prim[5], int64_
  * Synchronous. */
 int mf_totals(mf_grid_t g, int32_t event, double out[4]);
 
-/* Per-step kernel shape: cells per thread along each sweep axis (0 = automatic)
- * and threads per block (64, 128 or 256).  Used by the autotuner. */
+/* Per-step kernel shape (0 = automatic): seg[0] = chunks of 64 row items per
+ * wavefront of the x sweep, seg[1], seg[2] = cells per thread along y and z;
+ * block = threads per block (64, 128 or 256).  Used by the autotuner. */
 int mf_set_tuning(mf_grid_t g, const int32_t seg[3], int32_t block);
 
 /* Kernel timing: with enable != 0 every axis-sweep launch is bracketed by

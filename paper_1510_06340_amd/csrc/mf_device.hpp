@@ -88,24 +88,35 @@ template <typename T> struct EosIdeal {
     T q2;  // (1 + cs2)^2
     T c4;  // 4 cs2
 
-    // Returns E (possibly replaced) and the momentum to use, applying the guards.
-    __device__ __forceinline__ void guard(T& E, T& Mx, T& My, T& Mz, T& M2, bool& bad,
+    // Guards, applied only when some lane of the wavefront needs them (the
+    // branch is wave-uniform, so the common case costs two compares):
+    //  - E <= 0 or non-finite input: counted, evaluated as the zero state
+    //    (zero flux, e = p = v = 0) -- the caller zeroes its outputs when
+    //    'bad' is set;
+    //  - |M| > (1 - 1e-12) E: M scaled to that bound for this evaluation.
+    // Returns true if any lane of the wavefront was bad.
+    __device__ __forceinline__ bool guard(T& E, T& Mx, T& My, T& Mz, T& M2, bool& bad,
                                           Counts& cnt) const
     {
         M2 = Mx * Mx + My * My + Mz * Mz;
         bad = !((E > T(0)) & (E <= big_value<T>()) & (M2 <= big_value<T>()));
-        if (bad) {
-            cnt.bad++;
-            E = T(1);
-            Mx = T(0); My = T(0); Mz = T(0); M2 = T(0);
-        }
         const T Mlim = mmax<T>() * E;
-        if (M2 > Mlim * Mlim) {
-            const T s = Math<T>::div(Mlim, Math<T>::sqrt(M2));
-            Mx = Mx * s; My = My * s; Mz = Mz * s;
-            M2 = Mx * Mx + My * My + Mz * Mz;
-            cnt.floor_++;
+        const bool clamp = M2 > Mlim * Mlim;
+        bool any_bad = false;
+        if (__any(bad | clamp)) {
+            any_bad = __any(bad);
+            if (bad) {
+                cnt.bad++;
+                E = T(1);
+                Mx = T(0); My = T(0); Mz = T(0); M2 = T(0);
+            } else if (clamp) {
+                const T s = Math<T>::div(Mlim, Math<T>::sqrt(M2));
+                Mx = Mx * s; My = My * s; Mz = Mz * s;
+                M2 = Mx * Mx + My * My + Mz * Mz;
+                cnt.floor_++;
+            }
         }
+        return any_bad;
     }
 
     template <int D>
@@ -113,7 +124,7 @@ template <typename T> struct EosIdeal {
     {
         T E = u[0], Mx = u[1], My = u[2], Mz = u[3], M2;
         bool bad;
-        guard(E, Mx, My, Mz, M2, bad, cnt);
+        const bool any_bad = guard(E, Mx, My, Mz, M2, bad, cnt);
         const T s = Math<T>::sqrt(q2 * E * E - c4 * M2);
         const T r2 = T(2) * Math<T>::rcp(q * E + s);   // v_vec = r2 M
         const T e = E - r2 * M2;                       // E - M.v
@@ -125,7 +136,9 @@ template <typename T> struct EosIdeal {
         F[2] = My * vD;
         F[3] = Mz * vD;
         F[1 + D] = F[1 + D] + p;
-        if (bad) { F[0] = T(0); F[1] = T(0); F[2] = T(0); F[3] = T(0); }
+        if (any_bad) {
+            if (bad) { F[0] = T(0); F[1] = T(0); F[2] = T(0); F[3] = T(0); }
+        }
     }
 
     __device__ __forceinline__ void prim(const T u[4], T& e, T& p, T v[3], T& cs2,
@@ -133,14 +146,16 @@ template <typename T> struct EosIdeal {
     {
         T E = u[0], Mx = u[1], My = u[2], Mz = u[3], M2;
         bool bad;
-        guard(E, Mx, My, Mz, M2, bad, cnt);
+        const bool any_bad = guard(E, Mx, My, Mz, M2, bad, cnt);
         const T s = Math<T>::sqrt(q2 * E * E - c4 * M2);
         const T r2 = T(2) * Math<T>::rcp(q * E + s);
         v[0] = r2 * Mx; v[1] = r2 * My; v[2] = r2 * Mz;
         e = E - (Mx * v[0] + My * v[1] + Mz * v[2]);
         p = c * e;
         cs2 = c;
-        if (bad) { e = T(0); p = T(0); v[0] = T(0); v[1] = T(0); v[2] = T(0); }
+        if (any_bad) {
+            if (bad) { e = T(0); p = T(0); v[0] = T(0); v[1] = T(0); v[2] = T(0); }
+        }
     }
 };
 

@@ -70,6 +70,98 @@ __device__ __forceinline__ void flush_stats(unsigned long long* st, const Counts
     }
 }
 
+
+// Output of one cell of an axis sweep: write or accumulate L, or (last axis)
+// add the source, apply the Runge-Kutta combine and track the max speed.
+// uin = U[cell] of the stage input, Lp = L so far, ub = RK base state.
+template <typename T, bool JET, class Eos>
+__device__ __forceinline__ void emit_cell(const SweepArgs<T>& a, const Eos& eos, int64_t ij, const T uin[4],
+                                          const T Ld[4], const T Lp[4], const T ub[4], const double pos[3],
+                                          T& smax)
+{
+    if (a.mode == SW_WRITE) {
+#pragma unroll
+        for (int c = 0; c < 4; c++) a.L[c][ij] = Ld[c];
+        return;
+    }
+    if (a.mode == SW_ACCUM) {
+#pragma unroll
+        for (int c = 0; c < 4; c++) a.L[c][ij] = Lp[c] + Ld[c];
+        return;
+    }
+    T Lt[4];
+#pragma unroll
+    for (int c = 0; c < 4; c++) Lt[c] = Lp[c] + Ld[c];
+    if constexpr (JET) {
+        // S = v dE/dx G_sigma(x - x_jet(t)) (1, v, 0, 0) at the cell centre
+        const T x = T(pos[0] - a.jet_pos[0]);
+        const T y = T(pos[1] - a.jet_pos[1]);
+        const T z = T(pos[2] - a.jet_pos[2]);
+        const T G = T(a.jet_norm) * exp(-(x * x + y * y + z * z) * T(a.jet_inv2s2));
+        const T SE = T(a.jet_ve) * G;
+        Lt[0] = Lt[0] + SE;
+        Lt[1] = Lt[1] + T(a.jet_v) * SE;
+    }
+    T o[4];
+    const T dt = a.dt;
+    if (a.kind == RK_FIRST) {
+#pragma unroll
+        for (int c = 0; c < 4; c++) o[c] = uin[c] + dt * Lt[c];
+    } else if (a.kind == RK2_LAST) {
+#pragma unroll
+        for (int c = 0; c < 4; c++) o[c] = T(0.5) * ((ub[c] + uin[c]) + dt * Lt[c]);
+    } else if (a.kind == RK3_MID) {
+#pragma unroll
+        for (int c = 0; c < 4; c++) o[c] = (T(0.75) * ub[c] + T(0.25) * uin[c]) + T(0.25) * (dt * Lt[c]);
+    } else {
+        const T third = T(1.0 / 3.0), two3 = T(2.0 / 3.0);
+#pragma unroll
+        for (int c = 0; c < 4; c++) o[c] = (third * ub[c] + two3 * uin[c]) + two3 * (dt * Lt[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; c++) a.out[c][ij] = o[c];
+    if (a.want_smax) {
+        T e, p, v[3], cs2;
+        Counts cs;
+        eos.prim(o, e, p, v, cs2, cs);
+        smax = fmax(smax, max_speed(v, cs2));
+    }
+}
+
+// Ghost cells along a line of N cells: outflow copies the edge cell, periodic
+// wraps (for j in [-2, N+1]; N >= 2 needs one wrap, N == 1 maps to 0).
+__device__ __forceinline__ int ghost(int j, int N, int periodic)
+{
+    if (periodic) return (N == 1) ? 0 : (j < 0 ? j + N : (j >= N ? j - N : j));
+    return j < 0 ? 0 : (j >= N ? N - 1 : j);
+}
+
+// Lane i receives v from lane i-1; lane 0 receives 'carry' (DPP wave shift right).
+__device__ __forceinline__ double shift_up1(double v, double carry)
+{
+    const long long x = __double_as_longlong(v);
+    const long long c = __double_as_longlong(carry);
+    const int lo = __builtin_amdgcn_update_dpp((int)c, (int)x, 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(c >> 32), (int)(x >> 32), 0x138, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ float shift_up1(float v, float carry)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(carry), __float_as_int(v), 0x138, 0xf, 0xf,
+                                                      false));
+}
+
+__device__ __forceinline__ double lane63(double v)
+{
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)x, 63);
+    const int hi = __builtin_amdgcn_readlane((int)(x >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ float lane63(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63)); }
+
 template <typename T, int D, int LIM, class Eos, bool JET>
 __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a, Eos eos)
 {
@@ -84,13 +176,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a, Eos eos)
         const int64_t i_s = line / a.n_fast;
         const int64_t base = i_f * a.stride_f + i_s * a.stride_s;
         const int64_t sd = a.stride_d;
-        // ghost cells: outflow copies the edge cell, periodic wraps (N >= 2: one wrap suffices)
-        auto cell = [&](int j) -> int64_t {
-            int jj;
-            if (a.periodic) jj = (N == 1) ? 0 : (j < 0 ? j + N : (j >= N ? j - N : j));
-            else jj = j < 0 ? 0 : (j >= N ? N - 1 : j);
-            return base + (int64_t)jj * sd;
-        };
+        auto cell = [&](int j) -> int64_t { return base + (int64_t)ghost(j, N, a.periodic) * sd; };
 
         // The march starts two cells early: iteration j reconstructs cell j+1
         // and (from j = s0-1 on) solves interface j+1/2; cells are written
@@ -133,59 +219,101 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a, Eos eos)
             T Ld[4];
 #pragma unroll
             for (int c = 0; c < 4; c++) Ld[c] = -(Fn[c] - Fp[c]) * a.ac.inv_dx;
-
-            if (a.mode == SW_WRITE) {
-#pragma unroll
-                for (int c = 0; c < 4; c++) a.L[c][ij] = Ld[c];
-            } else if (a.mode == SW_ACCUM) {
-#pragma unroll
-                for (int c = 0; c < 4; c++) a.L[c][ij] = Lp[c] + Ld[c];
-            } else {
-                T Lt[4];
-#pragma unroll
-                for (int c = 0; c < 4; c++) Lt[c] = Lp[c] + Ld[c];
-                if constexpr (JET) {
-                    double pos[3];
-                    pos[D] = a.origin[D] + (j + 0.5) * a.dx[D];
-                    pos[a.axis_f] = a.origin[a.axis_f] + (i_f + 0.5) * a.dx[a.axis_f];
-                    pos[a.axis_s] = a.origin[a.axis_s] + (i_s + 0.5) * a.dx[a.axis_s];
-                    const T x = T(pos[0] - a.jet_pos[0]);
-                    const T y = T(pos[1] - a.jet_pos[1]);
-                    const T z = T(pos[2] - a.jet_pos[2]);
-                    const T G = T(a.jet_norm) * exp(-(x * x + y * y + z * z) * T(a.jet_inv2s2));
-                    const T SE = T(a.jet_ve) * G;
-                    Lt[0] = Lt[0] + SE;
-                    Lt[1] = Lt[1] + T(a.jet_v) * SE;
-                }
-                const T* uin = w0;  // U[j] after the window shift
-                T o[4];
-                const T dt = a.dt;
-                if (a.kind == RK_FIRST) {
-#pragma unroll
-                    for (int c = 0; c < 4; c++) o[c] = uin[c] + dt * Lt[c];
-                } else if (a.kind == RK2_LAST) {
-#pragma unroll
-                    for (int c = 0; c < 4; c++) o[c] = T(0.5) * ((ub[c] + uin[c]) + dt * Lt[c]);
-                } else if (a.kind == RK3_MID) {
-#pragma unroll
-                    for (int c = 0; c < 4; c++)
-                        o[c] = (T(0.75) * ub[c] + T(0.25) * uin[c]) + T(0.25) * (dt * Lt[c]);
-                } else {
-                    const T third = T(1.0 / 3.0), two3 = T(2.0 / 3.0);
-#pragma unroll
-                    for (int c = 0; c < 4; c++) o[c] = (third * ub[c] + two3 * uin[c]) + two3 * (dt * Lt[c]);
-                }
-#pragma unroll
-                for (int c = 0; c < 4; c++) a.out[c][ij] = o[c];
-                if (a.want_smax) {
-                    T e, p, v[3], cs2;
-                    Counts cs;
-                    eos.prim(o, e, p, v, cs2, cs);
-                    smax = fmax(smax, max_speed(v, cs2));
-                }
+            double pos[3] = {0.0, 0.0, 0.0};
+            if constexpr (JET) {
+                pos[D] = a.origin[D] + (j + 0.5) * a.dx[D];
+                pos[a.axis_f] = a.origin[a.axis_f] + (i_f + 0.5) * a.dx[a.axis_f];
+                pos[a.axis_s] = a.origin[a.axis_s] + (i_s + 0.5) * a.dx[a.axis_s];
             }
+            emit_cell<T, JET>(a, eos, ij, w0, Ld, Lp, ub, pos, smax);
 #pragma unroll
             for (int c = 0; c < 4; c++) Fp[c] = Fn[c];
+        }
+    }
+    flush_stats(a.stats, cnt, smax, a.mode == SW_FINAL && a.want_smax);
+}
+
+
+// ---------------------------------------------------------------------------
+// x sweep with lanes along x.  The rows of the grid are read as one stream of
+// items (row, x), x = -1..N (the cells whose faces feed the N+1 interfaces of
+// the row).  A wavefront takes 64 consecutive items per chunk: each lane
+// reconstructs its cell, receives its left neighbour's right face state by a
+// DPP lane shift (lane 0 from the previous chunk's lane 63), solves the
+// interface between them, receives the left neighbour's flux the same way and
+// writes L for the cell on its left.  All loads and stores are coalesced.
+// A wavefront owns items [s, s + 64 * seg) and starts two items early.
+// ---------------------------------------------------------------------------
+template <typename T, int LIM, class Eos>
+__global__ __launch_bounds__(256) void k_sweep_x(SweepArgs<T> a, Eos eos)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int N = a.N;
+    const int64_t P = (int64_t)N + 2;
+    const int64_t total = a.nlines * P;
+    const int64_t s = wave * 64 * (int64_t)a.seg;
+    Counts cnt;
+    T smax = T(0);
+    if (s < total) {
+        const int64_t e = min(s + 64 * (int64_t)a.seg, total);
+        int64_t it = s - 2 + lane;
+        int64_t row = 0;
+        int x = 0;
+        if (it >= 0) {
+            row = it / P;
+            x = (int)(it - row * P) - 1;
+        } else {
+            x = (int)(it + P) - 1;  // before the first row: never valid
+            row = -1;
+        }
+        T carryUR[4] = {T(0), T(0), T(0), T(0)};
+        T carryF[4] = {T(0), T(0), T(0), T(0)};
+        for (int64_t c0 = s - 2; c0 < e; c0 += 64) {
+            it = c0 + lane;
+            const bool valid = (it >= 0) & (it < e);
+            const int64_t base = (valid ? row : 0) * (int64_t)N;
+            const int xc = valid ? x : 0;
+            T w0[4], w1[4], w2[4];
+            load4(a.u, base + ghost(xc - 1, N, a.periodic), w0);
+            load4(a.u, base + ghost(xc, N, a.periodic), w1);
+            load4(a.u, base + ghost(xc + 1, N, a.periodic), w2);
+            T ULt[4], URt[4];
+            Counts ch;
+            hancock<0, LIM>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, ch);
+            if (valid & (it >= s)) add_counts(cnt, ch);
+            T URl[4];
+#pragma unroll
+            for (int c = 0; c < 4; c++) URl[c] = shift_up1(URt[c], carryUR[c]);
+            T F[4] = {T(0), T(0), T(0), T(0)};
+            if (valid & (x >= 0) & (it >= s - 1)) {   // interface x - 1/2
+                Counts cm;
+                musta<0>(URl, ULt, a.k, a.ac, F, eos, cm);
+                if (it >= s) add_counts(cnt, cm);
+            }
+            T Fl[4];
+#pragma unroll
+            for (int c = 0; c < 4; c++) Fl[c] = shift_up1(F[c], carryF[c]);
+            if (valid & (x >= 1) & (it >= s)) {   // cell x - 1
+                const int64_t ij = base + (x - 1);
+                T Ld[4], Lp[4] = {T(0), T(0), T(0), T(0)}, ub[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+                for (int c = 0; c < 4; c++) Ld[c] = -(F[c] - Fl[c]) * a.ac.inv_dx;
+                if (a.mode != SW_WRITE) load4((const T* const*)a.L, ij, Lp);
+                if (a.mode == SW_FINAL && a.kind != RK_FIRST) load4(a.u0, ij, ub);
+                const double pos[3] = {0.0, 0.0, 0.0};
+                emit_cell<T, false>(a, eos, ij, w0, Ld, Lp, ub, pos, smax);
+            }
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                carryUR[c] = lane63(URt[c]);
+                carryF[c] = lane63(F[c]);
+            }
+            x += 64;
+            while (x > N) {
+                x -= (int)P;
+                row++;
+            }
         }
     }
     flush_stats(a.stats, cnt, smax, a.mode == SW_FINAL && a.want_smax);
@@ -278,13 +406,14 @@ template <typename T, int D, int LIM, class Eos>
 static hipError_t launch_lim(bool jet, dim3 grid, dim3 block, hipStream_t s, const SweepArgs<T>& a,
                              const Eos& eos)
 {
-    if constexpr (D == 2) {
-        if (jet) {
-            hipLaunchKernelGGL((k_sweep<T, D, LIM, Eos, true>), grid, block, 0, s, a, eos);
-            return hipGetLastError();
-        }
+    if constexpr (D == 0) {
+        hipLaunchKernelGGL((k_sweep_x<T, LIM, Eos>), grid, block, 0, s, a, eos);
+    } else if constexpr (D == 2) {
+        if (jet) hipLaunchKernelGGL((k_sweep<T, D, LIM, Eos, true>), grid, block, 0, s, a, eos);
+        else hipLaunchKernelGGL((k_sweep<T, D, LIM, Eos, false>), grid, block, 0, s, a, eos);
+    } else {
+        hipLaunchKernelGGL((k_sweep<T, D, LIM, Eos, false>), grid, block, 0, s, a, eos);
     }
-    hipLaunchKernelGGL((k_sweep<T, D, LIM, Eos, false>), grid, block, 0, s, a, eos);
     return hipGetLastError();
 }
 

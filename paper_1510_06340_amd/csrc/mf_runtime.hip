@@ -127,6 +127,16 @@ AxisGeom axis_geom(const int32_t n[3], int d)
     return g;
 }
 
+// x sweep (lanes along x): chunks of 64 row items per wavefront, chosen to
+// give about two rounds of three wavefronts on every SIMD.
+int auto_chunks_x(const AxisGeom& g)
+{
+    const int64_t items = g.nlines * ((int64_t)g.N + 2);
+    const int64_t target_waves = 256LL * 4 * 3 * 2;
+    int64_t cpw = (items + 64 * target_waves - 1) / (64 * target_waves);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(cpw, 64));
+}
+
 // Cells per thread along the sweep axis: enough segments to put about three
 // wavefronts on every SIMD of the 256 compute units, but at least 16 cells
 // per segment (each segment recomputes two reconstructions and one interface).
@@ -174,7 +184,8 @@ int run_stage(mf_grid_s* g, Event& ev, unsigned long long* stats, void* const ui
         a.stride_s = geo.stride_s;
         a.N = geo.N;
         a.n_fast = geo.n_fast;
-        a.seg = g->seg_override[d] > 0 ? std::min(g->seg_override[d], geo.N) : auto_seg(geo);
+        if (d == 0) a.seg = g->seg_override[0] > 0 ? g->seg_override[0] : auto_chunks_x(geo);
+        else a.seg = g->seg_override[d] > 0 ? std::min(g->seg_override[d], geo.N) : auto_seg(geo);
         a.periodic = ev.d.bc[d] == MF_BC_PERIODIC;
         a.k = ev.d.musta_k;
         a.mode = d == 0 ? SW_WRITE : (d == 1 ? SW_ACCUM : SW_FINAL);
@@ -199,9 +210,16 @@ int run_stage(mf_grid_s* g, Event& ev, unsigned long long* stats, void* const ui
             a.dx[q] = ev.d.dx[q];
         }
         a.stats = stats;
-        const int64_t nseg = (geo.N + a.seg - 1) / a.seg;
         dim3 block(g->block);
-        dim3 grid((unsigned)((geo.nlines + g->block - 1) / g->block), (unsigned)nseg);
+        dim3 grid;
+        if (d == 0) {
+            const int64_t items = geo.nlines * ((int64_t)geo.N + 2);
+            const int64_t waves = (items + 64LL * a.seg - 1) / (64LL * a.seg);
+            grid = dim3((unsigned)((waves * 64 + g->block - 1) / g->block), 1);
+        } else {
+            const int64_t nseg = (geo.N + a.seg - 1) / a.seg;
+            grid = dim3((unsigned)((geo.nlines + g->block - 1) / g->block), (unsigned)nseg);
+        }
         mf_grid_s::Timed tm{d, nullptr, nullptr};
         if (g->profiling) {
             MF_HIP(g->take_event(&tm.start));

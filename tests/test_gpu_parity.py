@@ -115,7 +115,7 @@ def test_degenerate_and_thin_grids(n):
         assert max_rel_err(Ug, Uo) <= 1e-12
 
 
-@pytest.mark.parametrize("seg,block", [((1, 1, 1), 64), ((5, 7, 3), 128), ((1000, 1000, 1000), 256), ((16, 16, 16), 64)])
+@pytest.mark.parametrize("seg,block", [((1, 1, 1), 64), ((5, 7, 3), 128), ((1000, 1000, 1000), 256), ((2, 16, 16), 64)])
 def test_launch_shapes_agree(seg, block):
     """Every segment length and block size gives the same result (bitwise) and matches the oracle."""
     rng = np.random.default_rng(7)
@@ -209,6 +209,17 @@ def test_strict_mode_reports_unphysical_states():
     with pytest.raises(mf.MFError) as ei:
         gpu_run(w, U, flags=mf.MF_FLAG_STRICT)
     assert ei.value.code == mf.MF_ERR_UNPHYSICAL
+
+
+def test_hotspot_128_full_run_parity():
+    """The hot-spot workload at 128^3 (dx = 0.2) for the full 200 steps, FP64."""
+    w = I.hotspot_workload(n=128)
+    U = I.initial_state(w)
+    Ug, st = gpu_run(w, U)
+    Uo, sto = oracle_run(w, U)
+    assert max_rel_err(Ug, Uo) <= TOL64
+    assert st["n_floor"] == sto["n_floor"] and st["n_bad"] == 0
+    assert st["smax"] == pytest.approx(sto["smax"], rel=1e-10)
 
 
 def test_hotspot_256_full_size_one_step():
