@@ -86,6 +86,9 @@ def main(argv=None):
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time (0 = skip)")
     ap.add_argument("--seg", type=int, nargs=3, default=None, help="cells per thread along x, y, z")
     ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="before timing, copy this many MiB device-to-device (a kernel of known traffic "
+                         "for scaling hardware byte counters)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -110,6 +113,13 @@ def main(argv=None):
     if args.seg is not None or args.block != 256:
         g.set_tuning(args.seg or (0, 0, 0), args.block)
 
+    if args.calib_copy_mb > 0:
+        nel = args.calib_copy_mb * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.warmup > 0:
         g.step(w.dt, args.warmup, stats=False)
     torch.cuda.synchronize()

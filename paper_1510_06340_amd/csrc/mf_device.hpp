@@ -83,79 +83,98 @@ struct Counts {
 // root below one of  c|M| v^2 - (1+c) E v + |M| = 0:
 //   v_vec = 2 M / ((1+c) E + sqrt((1+c)^2 E^2 - 4 c |M|^2)),  e = E - M.v.
 template <typename T> struct EosIdeal {
-    T c;   // cs2
-    T q;   // 1 + cs2
-    T q2;  // (1 + cs2)^2
-    T c4;  // 4 cs2
+    T c;    // cs2
+    T qh;   // (1 + cs2) / 2
+    T q2q;  // (1 + cs2)^2 / 4
 
-    // Guards, applied only when some lane of the wavefront needs them (the
-    // branch is wave-uniform, so the common case costs two compares):
-    //  - E <= 0 or non-finite input: counted, evaluated as the zero state
-    //    (zero flux, e = p = v = 0) -- the caller zeroes its outputs when
-    //    'bad' is set;
-    //  - |M| > (1 - 1e-12) E: M scaled to that bound for this evaluation.
-    // Returns true if any lane of the wavefront was bad.
-    __device__ __forceinline__ bool guard(T& E, T& Mx, T& My, T& Mz, T& M2, bool& bad,
-                                          Counts& cnt) const
+    static EosIdeal make(double cs2)
     {
-        M2 = Mx * Mx + My * My + Mz * Mz;
-        bad = !((E > T(0)) & (E <= big_value<T>()) & (M2 <= big_value<T>()));
-        const T Mlim = mmax<T>() * E;
-        const bool clamp = M2 > Mlim * Mlim;
-        bool any_bad = false;
-        if (__any(bad | clamp)) {
-            any_bad = __any(bad);
-            if (bad) {
-                cnt.bad++;
-                E = T(1);
-                Mx = T(0); My = T(0); Mz = T(0); M2 = T(0);
-            } else if (clamp) {
-                const T s = Math<T>::div(Mlim, Math<T>::sqrt(M2));
-                Mx = Mx * s; My = My * s; Mz = Mz * s;
-                M2 = Mx * Mx + My * My + Mz * Mz;
-                cnt.floor_++;
-            }
+        EosIdeal e;
+        e.c = (T)cs2;
+        e.qh = (T)(0.5 * (1.0 + cs2));
+        e.q2q = (T)(0.25 * (1.0 + cs2) * (1.0 + cs2));
+        return e;
+    }
+
+    // With the halved radicand d = ((1+c)/2)^2 E^2 - c |M|^2 (= D/4, exact
+    // scaling) the velocity is v_vec = M / ((1+c)/2 E + sqrt(d)).
+    __device__ __forceinline__ T inv_half_den(T E, T E2, T M2) const
+    {
+        const T sd = Math<T>::sqrt(q2q * E2 - c * M2);
+        return Math<T>::rcp(qh * E + sd);   // = 2 / ((1+c)E + sqrt(D))
+    }
+
+    // Guards (outside the common path): E <= 0 or non-finite input is counted
+    // and evaluated as the zero state (zero flux, e = p = v = 0); |M| above
+    // (1 - 1e-12) E is scaled down to that bound for this evaluation.
+    // Returns false for the zero state.
+    __device__ __forceinline__ bool fixup(T& E, T& Mx, T& My, T& Mz, T& M2, Counts& cnt) const
+    {
+        if (!((E > T(0)) & (E <= big_value<T>()) & (M2 <= big_value<T>()))) {
+            cnt.bad++;
+            return false;
         }
-        return any_bad;
+        const T Mlim = mmax<T>() * E;
+        if (M2 > Mlim * Mlim) {
+            const T s = Math<T>::div(Mlim, Math<T>::sqrt(M2));
+            Mx = Mx * s; My = My * s; Mz = Mz * s;
+            M2 = Mx * Mx + My * My + Mz * Mz;
+            cnt.floor_++;
+        }
+        return true;
     }
 
     template <int D>
-    __device__ __forceinline__ void flux(const T u[4], T F[4], Counts& cnt) const
+    __device__ __forceinline__ void flux_core(T E, T Mx, T My, T Mz, T M2, T F[4]) const
     {
-        T E = u[0], Mx = u[1], My = u[2], Mz = u[3], M2;
-        bool bad;
-        const bool any_bad = guard(E, Mx, My, Mz, M2, bad, cnt);
-        const T s = Math<T>::sqrt(q2 * E * E - c4 * M2);
-        const T r2 = T(2) * Math<T>::rcp(q * E + s);   // v_vec = r2 M
-        const T e = E - r2 * M2;                       // E - M.v
+        const T r = inv_half_den(E, E * E, M2);   // v_vec = r M
+        const T e = E - r * M2;                   // E - M.v
         const T p = c * e;
         const T MD = (D == 0) ? Mx : ((D == 1) ? My : Mz);
-        const T vD = r2 * MD;
+        const T vD = r * MD;
         F[0] = (E + p) * vD;
         F[1] = Mx * vD;
         F[2] = My * vD;
         F[3] = Mz * vD;
         F[1 + D] = F[1 + D] + p;
-        if (any_bad) {
-            if (bad) { F[0] = T(0); F[1] = T(0); F[2] = T(0); F[3] = T(0); }
+    }
+
+    // F = F_D(U) after con2prim.  The common path has no guard branches; when
+    // any lane of the wavefront holds a state that needs a guard, those lanes
+    // are re-evaluated on the slow path.
+    template <int D>
+    __device__ __forceinline__ void flux(const T u[4], T F[4], Counts& cnt) const
+    {
+        const T E = u[0], Mx = u[1], My = u[2], Mz = u[3];
+        const T M2 = Mx * Mx + My * My + Mz * Mz;
+        const T Mlim = mmax<T>() * E;
+        const bool ok = (E > T(0)) & (E <= big_value<T>()) & (M2 <= Mlim * Mlim);
+        flux_core<D>(E, Mx, My, Mz, M2, F);
+        if (__any(!ok)) {
+            if (!ok) {
+                T Ef = E, mx = Mx, my = My, mz = Mz, m2 = M2;
+                if (fixup(Ef, mx, my, mz, m2, cnt)) {
+                    flux_core<D>(Ef, mx, my, mz, m2, F);
+                } else {
+                    F[0] = T(0); F[1] = T(0); F[2] = T(0); F[3] = T(0);
+                }
+            }
         }
     }
 
-    __device__ __forceinline__ void prim(const T u[4], T& e, T& p, T v[3], T& cs2,
-                                         Counts& cnt) const
+    __device__ __forceinline__ void prim(const T u[4], T& e, T& p, T v[3], T& cs2, Counts& cnt) const
     {
-        T E = u[0], Mx = u[1], My = u[2], Mz = u[3], M2;
-        bool bad;
-        const bool any_bad = guard(E, Mx, My, Mz, M2, bad, cnt);
-        const T s = Math<T>::sqrt(q2 * E * E - c4 * M2);
-        const T r2 = T(2) * Math<T>::rcp(q * E + s);
-        v[0] = r2 * Mx; v[1] = r2 * My; v[2] = r2 * Mz;
+        T E = u[0], Mx = u[1], My = u[2], Mz = u[3];
+        T M2 = Mx * Mx + My * My + Mz * Mz;
+        cs2 = c;
+        if (!fixup(E, Mx, My, Mz, M2, cnt)) {
+            e = T(0); p = T(0); v[0] = T(0); v[1] = T(0); v[2] = T(0);
+            return;
+        }
+        const T r = inv_half_den(E, E * E, M2);
+        v[0] = r * Mx; v[1] = r * My; v[2] = r * Mz;
         e = E - (Mx * v[0] + My * v[1] + Mz * v[2]);
         p = c * e;
-        cs2 = c;
-        if (any_bad) {
-            if (bad) { e = T(0); p = T(0); v[0] = T(0); v[1] = T(0); v[2] = T(0); }
-        }
     }
 };
 
@@ -174,20 +193,28 @@ __device__ __forceinline__ T limiter(T a, T b)
     } else if constexpr (LIM == LIM_VANALBADA) {
         const T den = a * a + b * b;
         return (den > T(0)) ? (a * b * (a + b)) / den : T(0);
-    } else {
+    } else if constexpr (LIM == LIM_VANLEER) {
+        // 2ab / (a + b) = 2|a||b| / (|a| + |b|) with the sign of a, for equal signs
         const bool same = (fmin(a, b) > T(0)) | (fmax(a, b) < T(0));
         const T aa = fabs(a), bb = fabs(b);
+        const T m = Math<T>::div(T(2) * aa * bb, aa + bb);
+        return same ? copysign(m, a) : T(0);
+    } else {
+        // With s = sign(a): s b < 0 when the signs differ, and s b = 0 or
+        // |a| = 0 when one difference vanishes, so max(0, min(..)) is the
+        // "same sign" test; the result carries the sign s.
+        const T s = copysign(T(1), a);
+        const T aa = fabs(a);
+        const T sb = s * b;
         T m;
         if constexpr (LIM == LIM_MINMOD) {
-            m = fmin(aa, bb);
+            m = fmin(aa, sb);
         } else if constexpr (LIM == LIM_SUPERBEE) {
-            m = fmax(fmin(T(2) * bb, aa), fmin(bb, T(2) * aa));
-        } else if constexpr (LIM == LIM_MC) {
-            m = fmin(fmin(T(2) * aa, T(2) * bb), T(0.5) * fabs(a + b));
-        } else {  // LIM_VANLEER: 2ab / (a + b) = 2|a||b| / (|a| + |b|) for equal signs
-            m = Math<T>::div(T(2) * aa * bb, aa + bb);
+            m = fmax(fmin(T(2) * sb, aa), fmin(sb, T(2) * aa));
+        } else {  // LIM_MC
+            m = fmin(T(2) * fmin(aa, sb), T(0.5) * (aa + sb));
         }
-        return same ? copysign(m, a) : T(0);
+        return s * fmax(m, T(0));
     }
 }
 

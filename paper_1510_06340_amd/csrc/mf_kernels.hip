@@ -163,7 +163,7 @@ __device__ __forceinline__ double lane63(double v)
 __device__ __forceinline__ float lane63(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63)); }
 
 template <typename T, int D, int LIM, class Eos, bool JET>
-__global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a, Eos eos)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep(SweepArgs<T> a, Eos eos)
 {
     const int64_t line = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int N = a.N;
@@ -192,9 +192,6 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a, Eos eos)
             load4(a.u, cell(j + 2), w2);
             const int64_t ij = base + (int64_t)j * sd;
             const bool body = j >= s0;
-            T Lp[4], ub[4];
-            if (body && a.mode != SW_WRITE) load4((const T* const*)a.L, ij, Lp);
-            if (body && a.mode == SW_FINAL && a.kind != RK_FIRST) load4(a.u0, ij, ub);
 
             // cell j+1; counted once over all segments of the line (cells -1..N)
             Counts ch;
@@ -216,7 +213,9 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a, Eos eos)
                 continue;
             }
 
-            T Ld[4];
+            T Ld[4], Lp[4] = {T(0), T(0), T(0), T(0)}, ub[4] = {T(0), T(0), T(0), T(0)};
+            if (a.mode != SW_WRITE) load4((const T* const*)a.L, ij, Lp);
+            if (a.mode == SW_FINAL && a.kind != RK_FIRST) load4(a.u0, ij, ub);
 #pragma unroll
             for (int c = 0; c < 4; c++) Ld[c] = -(Fn[c] - Fp[c]) * a.ac.inv_dx;
             double pos[3] = {0.0, 0.0, 0.0};
@@ -245,7 +244,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a, Eos eos)
 // A wavefront owns items [s, s + 64 * seg) and starts two items early.
 // ---------------------------------------------------------------------------
 template <typename T, int LIM, class Eos>
-__global__ __launch_bounds__(256) void k_sweep_x(SweepArgs<T> a, Eos eos)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_x(SweepArgs<T> a, Eos eos)
 {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;

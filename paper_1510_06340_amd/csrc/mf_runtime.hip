@@ -163,11 +163,7 @@ template <typename T>
 int run_stage(mf_grid_s* g, Event& ev, unsigned long long* stats, void* const uin[4], void* const u0[4],
               void* const out[4], int kind, double dt, double ts, bool want_smax)
 {
-    EosIdeal<T> eos;
-    eos.c = (T)g->cs2;
-    eos.q = (T)(1.0 + g->cs2);
-    eos.q2 = (T)((1.0 + g->cs2) * (1.0 + g->cs2));
-    eos.c4 = (T)(4.0 * g->cs2);
+    const EosIdeal<T> eos = EosIdeal<T>::make(g->cs2);
     for (int d = 0; d < 3; d++) {
         const AxisGeom geo = axis_geom(ev.d.n, d);
         SweepArgs<T> a;
@@ -521,15 +517,14 @@ int mf_con2prim(mf_grid_t g, const void* const U[4], void* const prim[5], int64_
         for (int c = 0; c < 4; c++) a.U[c] = (const float*)U[c];
         for (int c = 0; c < 5; c++) a.prim[c] = (float*)prim[c];
         a.iters = iters_dev; a.n = n; a.stats = stats;
-        EosIdeal<float> eos{(float)g->cs2, (float)(1.0 + g->cs2), (float)((1.0 + g->cs2) * (1.0 + g->cs2)),
-                            (float)(4.0 * g->cs2)};
+        const EosIdeal<float> eos = EosIdeal<float>::make(g->cs2);
         e = launch_con2prim<float>(n, g->stream, a, eos);
     } else {
         C2PArgs<double> a;
         for (int c = 0; c < 4; c++) a.U[c] = (const double*)U[c];
         for (int c = 0; c < 5; c++) a.prim[c] = (double*)prim[c];
         a.iters = iters_dev; a.n = n; a.stats = stats;
-        EosIdeal<double> eos{g->cs2, 1.0 + g->cs2, (1.0 + g->cs2) * (1.0 + g->cs2), 4.0 * g->cs2};
+        const EosIdeal<double> eos = EosIdeal<double>::make(g->cs2);
         e = launch_con2prim<double>(n, g->stream, a, eos);
     }
     if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("con2prim launch: ") + hipGetErrorString(e));
