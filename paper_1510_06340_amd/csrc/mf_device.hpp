@@ -83,6 +83,7 @@ struct Counts {
 // root below one of  c|M| v^2 - (1+c) E v + |M| = 0:
 //   v_vec = 2 M / ((1+c) E + sqrt((1+c)^2 E^2 - 4 c |M|^2)),  e = E - M.v.
 template <typename T> struct EosIdeal {
+    static constexpr int kWaves = 4;  // sweep kernels fit 128 VGPRs without spilling
     T c;    // cs2
     T qh;   // (1 + cs2) / 2
     T q2q;  // (1 + cs2)^2 / 4
@@ -175,6 +176,173 @@ template <typename T> struct EosIdeal {
         v[0] = r * Mx; v[1] = r * My; v[2] = r * Mz;
         e = E - (Mx * v[0] + My * v[1] + Mz * v[2]);
         p = c * e;
+    }
+};
+
+
+// ---------------------------------------------------------------------------
+// Tabulated p(e): monotone piecewise-cubic Hermite interpolation on nodes
+// e_i with node slopes m_i (Fritsch-Carlson), p = p_0 e / e_0 below the first
+// node and linear with the end slope above the last.  One 32-byte record per
+// node: (e_i, p_i, m_i, 1 / (e_{i+1} - e_i)).
+//
+// con2prim (Sec. 2.6): the fixed point v = |M| / (E + p(E - |M| v)) is the
+// root of g(e) = e - E + |M|^2 / (E + p(e)) on the bracket [E (1 - m^2), E],
+// m = |M| / E (g is increasing there for dp/de < 1).  Safeguarded Newton from
+// the bracket midpoint: a step that leaves the current bracket is replaced by
+// bisection; the bracket shrinks with the sign of g; stop when
+// |de| <= 1e-12 e.  FP64 only.
+// ---------------------------------------------------------------------------
+struct EosTable {
+    static constexpr int kWaves = 2;
+    const double4* rec;  // n records
+    int32_t n;
+    int32_t log_uniform; // index from log2(e) (then a +-1 fix-up); else bisection
+    float lg0;           // log2 e_0
+    float inv_dlg;       // (n - 1) / (log2 e_{n-1} - log2 e_0)
+    double e0, p0_e0;    // first node and p_0 / e_0
+    double elast, plast, mlast;
+    int32_t max_iter;
+
+    __device__ __forceinline__ void eval(double e, double& p, double& dp) const
+    {
+        if (!(e > e0)) {
+            p = p0_e0 * e;
+            dp = p0_e0;
+            return;
+        }
+        if (e >= elast) {
+            p = plast + mlast * (e - elast);
+            dp = mlast;
+            return;
+        }
+        int i;
+        double4 r0, r1;
+        if (log_uniform) {
+            const float l = __builtin_amdgcn_logf((float)e);  // log2, about 1 ulp
+            i = (int)((l - lg0) * inv_dlg);
+            i = i < 0 ? 0 : (i > n - 2 ? n - 2 : i);
+            r0 = rec[i];
+            r1 = rec[i + 1];
+            if (e < r0.x && i > 0) {
+                i--;
+                r1 = r0;
+                r0 = rec[i];
+            } else if (e >= r1.x && i < n - 2) {
+                i++;
+                r0 = r1;
+                r1 = rec[i + 1];
+            }
+        } else {
+            int lo = 0, hi = n - 1;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (rec[mid].x <= e) lo = mid;
+                else hi = mid;
+            }
+            i = lo;
+            r0 = rec[i];
+            r1 = rec[i + 1];
+        }
+        const double h = r1.x - r0.x;
+        const double t = (e - r0.x) * r0.w;
+        const double t2 = t * t, t3 = t2 * t;
+        const double h00 = 2.0 * t3 - 3.0 * t2 + 1.0;
+        const double h10 = t3 - 2.0 * t2 + t;
+        const double h01 = -2.0 * t3 + 3.0 * t2;
+        const double h11 = t3 - t2;
+        p = h00 * r0.y + h10 * h * r0.z + h01 * r1.y + h11 * h * r1.z;
+        const double d00 = (6.0 * t2 - 6.0 * t) * r0.w;
+        const double d10 = 3.0 * t2 - 4.0 * t + 1.0;
+        const double d11 = 3.0 * t2 - 2.0 * t;
+        dp = d00 * (r0.y - r1.y) + d10 * r0.z + d11 * r1.z;
+    }
+
+    // Root e of g on the bracket, starting from e_start (inside the bracket).
+    __device__ __forceinline__ double solve(double E, double M2, double e_start, Counts& cnt) const
+    {
+        double lo = E - M2 * Math<double>::rcp(E);
+        double hi = E;
+        double e = e_start;
+        for (int it = 0; it < max_iter; it++) {
+            double p, dp;
+            eval(e, p, dp);
+            const double iw = Math<double>::rcp(E + p);
+            const double g = (e - E) + M2 * iw;
+            if (g > 0.0) hi = e;
+            else lo = e;
+            const double gp = 1.0 - M2 * dp * iw * iw;
+            double en = e - g * Math<double>::rcp(gp);
+            if (!(en > lo && en < hi)) en = 0.5 * (lo + hi);
+            cnt.iters++;
+            const bool done = fabs(en - e) <= 1e-12 * en;
+            e = en;
+            if (done) break;
+        }
+        return e;
+    }
+
+    __device__ __forceinline__ double recover(double E, double M2, Counts& cnt) const
+    {
+        if (M2 == 0.0) return E;
+        const double lo = E - M2 * Math<double>::rcp(E);
+        return solve(E, M2, 0.5 * (lo + E), cnt);
+    }
+
+    __device__ __forceinline__ bool fixup(double& E, double& Mx, double& My, double& Mz, double& M2,
+                                          Counts& cnt) const
+    {
+        if (!((E > 0.0) & (E <= big_value<double>()) & (M2 <= big_value<double>()))) {
+            cnt.bad++;
+            return false;
+        }
+        const double Mlim = mmax<double>() * E;
+        if (M2 > Mlim * Mlim) {
+            const double s = Mlim / Math<double>::sqrt(M2);
+            Mx = Mx * s; My = My * s; Mz = Mz * s;
+            M2 = Mx * Mx + My * My + Mz * Mz;
+            cnt.floor_++;
+        }
+        return true;
+    }
+
+    template <int D>
+    __device__ __forceinline__ void flux(const double u[4], double F[4], Counts& cnt) const
+    {
+        double E = u[0], Mx = u[1], My = u[2], Mz = u[3];
+        double M2 = Mx * Mx + My * My + Mz * Mz;
+        if (!fixup(E, Mx, My, Mz, M2, cnt)) {
+            F[0] = 0.0; F[1] = 0.0; F[2] = 0.0; F[3] = 0.0;
+            return;
+        }
+        const double e = recover(E, M2, cnt);
+        double p, dp;
+        eval(e, p, dp);
+        const double w = E + p;
+        const double MD = (D == 0) ? Mx : ((D == 1) ? My : Mz);
+        const double vD = MD * Math<double>::rcp(w);
+        F[0] = w * vD;
+        F[1] = Mx * vD;
+        F[2] = My * vD;
+        F[3] = Mz * vD;
+        F[1 + D] = F[1 + D] + p;
+    }
+
+    __device__ __forceinline__ void prim(const double u[4], double& e, double& p, double v[3], double& cs2,
+                                         Counts& cnt) const
+    {
+        double E = u[0], Mx = u[1], My = u[2], Mz = u[3];
+        double M2 = Mx * Mx + My * My + Mz * Mz;
+        if (!fixup(E, Mx, My, Mz, M2, cnt)) {
+            e = 0.0; p = 0.0; v[0] = 0.0; v[1] = 0.0; v[2] = 0.0; cs2 = 0.0;
+            return;
+        }
+        e = recover(E, M2, cnt);
+        double dp;
+        eval(e, p, dp);
+        const double iw = Math<double>::rcp(E + p);
+        v[0] = Mx * iw; v[1] = My * iw; v[2] = Mz * iw;
+        cs2 = dp;
     }
 };
 

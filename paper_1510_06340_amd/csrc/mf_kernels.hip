@@ -13,6 +13,8 @@
 // Runge-Kutta combine and (last stage) reduces the max characteristic speed.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "mf_device.hpp"
 #include "mf_kernels.hpp"
 
@@ -94,7 +96,8 @@ __device__ __forceinline__ void emit_cell(const SweepArgs<T>& a, const Eos& eos,
     for (int c = 0; c < 4; c++) Lt[c] = Lp[c] + Ld[c];
     if constexpr (JET) {
         // S = v dE/dx G_sigma(x - x_jet(t)) (1, v, 0, 0) at the cell centre
-        const T x = T(pos[0] - a.jet_pos[0]);
+        const double xj = a.jet_pos[0] + (a.t_ptr ? a.jet_v * (*a.t_ptr + a.t_off) : 0.0);
+        const T x = T(pos[0] - xj);
         const T y = T(pos[1] - a.jet_pos[1]);
         const T z = T(pos[2] - a.jet_pos[2]);
         const T G = T(a.jet_norm) * exp(-(x * x + y * y + z * z) * T(a.jet_inv2s2));
@@ -162,76 +165,81 @@ __device__ __forceinline__ double lane63(double v)
 
 __device__ __forceinline__ float lane63(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63)); }
 
+// One thread's segment [s0, s0 + seg) of grid line 'line' along axis D.
 template <typename T, int D, int LIM, class Eos, bool JET>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep(SweepArgs<T> a, Eos eos)
+__device__ __forceinline__ void sweep_line(const SweepArgs<T>& a, const Eos& eos, int64_t line, int s0,
+                                           Counts& cnt, T& smax)
 {
-    const int64_t line = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int N = a.N;
-    const int s0 = blockIdx.y * a.seg;
-    Counts cnt;
-    T smax = T(0);
-    if (line < a.nlines && s0 < N) {
-        const int s1 = min(s0 + a.seg, N);
-        const int64_t i_f = line % a.n_fast;
-        const int64_t i_s = line / a.n_fast;
-        const int64_t base = i_f * a.stride_f + i_s * a.stride_s;
-        const int64_t sd = a.stride_d;
-        auto cell = [&](int j) -> int64_t { return base + (int64_t)ghost(j, N, a.periodic) * sd; };
+    if (!(line < a.nlines && s0 < N)) return;
+    const int s1 = min(s0 + a.seg, N);
+    const int64_t i_f = line % a.n_fast;
+    const int64_t i_s = line / a.n_fast;
+    const int64_t base = i_f * a.stride_f + i_s * a.stride_s;
+    const int64_t sd = a.stride_d;
+    auto cell = [&](int j) -> int64_t { return base + (int64_t)ghost(j, N, a.periodic) * sd; };
 
-        // The march starts two cells early: iteration j reconstructs cell j+1
-        // and (from j = s0-1 on) solves interface j+1/2; cells are written
-        // from j = s0 on.  Warm-up and body share one instance of the code,
-        // so results do not depend on the segmentation.
-        T w0[4], w1[4], w2[4];
-        T ULt[4], URt[4], URp[4], Fp[4], Fn[4];
-        load4(a.u, cell(s0 - 2), w1);
-        load4(a.u, cell(s0 - 1), w2);
-        for (int j = s0 - 2; j < s1; j++) {
-            copy4(w1, w0);
-            copy4(w2, w1);
-            load4(a.u, cell(j + 2), w2);
-            const int64_t ij = base + (int64_t)j * sd;
-            const bool body = j >= s0;
+    // The march starts two cells early: iteration j reconstructs cell j+1
+    // and (from j = s0-1 on) solves interface j+1/2; cells are written
+    // from j = s0 on.  Warm-up and body share one instance of the code,
+    // so results do not depend on the segmentation.
+    T w0[4], w1[4], w2[4];
+    T ULt[4], URt[4], URp[4], Fp[4], Fn[4];
+    load4(a.u, cell(s0 - 2), w1);
+    load4(a.u, cell(s0 - 1), w2);
+    for (int j = s0 - 2; j < s1; j++) {
+        copy4(w1, w0);
+        copy4(w2, w1);
+        load4(a.u, cell(j + 2), w2);
+        const int64_t ij = base + (int64_t)j * sd;
+        const bool body = j >= s0;
 
-            // cell j+1; counted once over all segments of the line (cells -1..N)
-            Counts ch;
-            hancock<D, LIM>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, ch);
-            const int c1 = j + 1;
-            if (c1 == s0 - 1 ? s0 == 0 : (c1 < s1 || c1 == N)) add_counts(cnt, ch);
-            if (j == s0 - 2) {
-                copy4(URt, URp);
-                continue;
-            }
-            // interface j + 1/2; counted once over all segments (interfaces -1/2..N-1/2)
-            Counts cm;
-            musta<D>(URp, ULt, a.k, a.ac, Fn, eos, cm);
-            if (body || s0 == 0) add_counts(cnt, cm);
+        // cell j+1; counted once over all segments of the line (cells -1..N)
+        Counts ch;
+        hancock<D, LIM>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, ch);
+        const int c1 = j + 1;
+        if (c1 == s0 - 1 ? s0 == 0 : (c1 < s1 || c1 == N)) add_counts(cnt, ch);
+        if (j == s0 - 2) {
             copy4(URt, URp);
-            if (!body) {
-#pragma unroll
-                for (int c = 0; c < 4; c++) Fp[c] = Fn[c];
-                continue;
-            }
-
-            T Ld[4], Lp[4] = {T(0), T(0), T(0), T(0)}, ub[4] = {T(0), T(0), T(0), T(0)};
-            if (a.mode != SW_WRITE) load4((const T* const*)a.L, ij, Lp);
-            if (a.mode == SW_FINAL && a.kind != RK_FIRST) load4(a.u0, ij, ub);
-#pragma unroll
-            for (int c = 0; c < 4; c++) Ld[c] = -(Fn[c] - Fp[c]) * a.ac.inv_dx;
-            double pos[3] = {0.0, 0.0, 0.0};
-            if constexpr (JET) {
-                pos[D] = a.origin[D] + (j + 0.5) * a.dx[D];
-                pos[a.axis_f] = a.origin[a.axis_f] + (i_f + 0.5) * a.dx[a.axis_f];
-                pos[a.axis_s] = a.origin[a.axis_s] + (i_s + 0.5) * a.dx[a.axis_s];
-            }
-            emit_cell<T, JET>(a, eos, ij, w0, Ld, Lp, ub, pos, smax);
+            continue;
+        }
+        // interface j + 1/2; counted once over all segments (interfaces -1/2..N-1/2)
+        Counts cm;
+        musta<D>(URp, ULt, a.k, a.ac, Fn, eos, cm);
+        if (body || s0 == 0) add_counts(cnt, cm);
+        copy4(URt, URp);
+        if (!body) {
 #pragma unroll
             for (int c = 0; c < 4; c++) Fp[c] = Fn[c];
+            continue;
         }
+
+        T Ld[4], Lp[4] = {T(0), T(0), T(0), T(0)}, ub[4] = {T(0), T(0), T(0), T(0)};
+        if (a.mode != SW_WRITE) load4((const T* const*)a.L, ij, Lp);
+        if (a.mode == SW_FINAL && a.kind != RK_FIRST) load4(a.u0, ij, ub);
+#pragma unroll
+        for (int c = 0; c < 4; c++) Ld[c] = -(Fn[c] - Fp[c]) * a.ac.inv_dx;
+        double pos[3] = {0.0, 0.0, 0.0};
+        if constexpr (JET && D == 2) {  // z sweep: the line index runs over (x, y)
+            pos[0] = a.origin[0] + (i_f + 0.5) * a.dx[0];
+            pos[1] = a.origin[1] + (i_s + 0.5) * a.dx[1];
+            pos[2] = a.origin[2] + (j + 0.5) * a.dx[2];
+        }
+        emit_cell<T, JET>(a, eos, ij, w0, Ld, Lp, ub, pos, smax);
+#pragma unroll
+        for (int c = 0; c < 4; c++) Fp[c] = Fn[c];
     }
-    flush_stats(a.stats, cnt, smax, a.mode == SW_FINAL && a.want_smax);
 }
 
+template <typename T, int D, int LIM, class Eos, bool JET>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Eos::kWaves))) void k_sweep(SweepArgs<T> a, Eos eos)
+{
+    const int64_t line = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    Counts cnt;
+    T smax = T(0);
+    sweep_line<T, D, LIM, Eos, JET>(a, eos, line, (int)blockIdx.y * a.seg, cnt, smax);
+    flush_stats(a.stats, cnt, smax, a.mode == SW_FINAL && a.want_smax);
+}
 
 // ---------------------------------------------------------------------------
 // x sweep with lanes along x.  The rows of the grid are read as one stream of
@@ -243,17 +251,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 // writes L for the cell on its left.  All loads and stores are coalesced.
 // A wavefront owns items [s, s + 64 * seg) and starts two items early.
 // ---------------------------------------------------------------------------
+// Wavefront 'wave' of the x sweep: items [wave * 64 * seg, ...) of the row stream.
 template <typename T, int LIM, class Eos>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_x(SweepArgs<T> a, Eos eos)
+__device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& eos, int64_t wave, int lane,
+                                             Counts& cnt, T& smax)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int N = a.N;
     const int64_t P = (int64_t)N + 2;
     const int64_t total = a.nlines * P;
     const int64_t s = wave * 64 * (int64_t)a.seg;
-    Counts cnt;
-    T smax = T(0);
     if (s < total) {
         const int64_t e = min(s + 64 * (int64_t)a.seg, total);
         int64_t it = s - 2 + lane;
@@ -315,7 +321,73 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             }
         }
     }
+}
+
+template <typename T, int LIM, class Eos>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Eos::kWaves))) void k_sweep_x(SweepArgs<T> a, Eos eos)
+{
+    Counts cnt;
+    T smax = T(0);
+    sweep_x_wave<T, LIM, Eos>(a, eos, ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6, threadIdx.x & 63, cnt,
+                              smax);
     flush_stats(a.stats, cnt, smax, a.mode == SW_FINAL && a.want_smax);
+}
+
+
+// ---------------------------------------------------------------------------
+// Batched sweeps: one persistent launch per axis sweep over every event of a
+// handle.  The tiles of event e are [tile_start[e], tile_start[e+1]); a tile
+// is one block's work of the per-event kernels (256 or 128 lines x one
+// segment for y and z, block/64 wavefronts of row items for x).  Blocks pop
+// tiles from an atomic counter until the queue is empty, so uneven events
+// balance across the compute units; the arithmetic per cell is that of the
+// per-event kernels.
+// ---------------------------------------------------------------------------
+template <typename T, int D, int LIM, class Eos, bool JET>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Eos::kWaves)))
+void k_batch_sweep(const SweepArgs<T>* __restrict__ tab, const int64_t* __restrict__ tile_start, int ne,
+                   unsigned int* counter, Eos eos)
+{
+    __shared__ int64_t sh_tile;
+    const int64_t total = tile_start[ne];
+    for (;;) {
+        if (threadIdx.x == 0) sh_tile = (int64_t)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int64_t tile = sh_tile;
+        __syncthreads();
+        if (tile >= total) break;
+        int lo = 0, hi = ne;  // tile_start[lo] <= tile < tile_start[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (tile_start[mid] <= tile) lo = mid;
+            else hi = mid;
+        }
+        const SweepArgs<T>& a = tab[lo];
+        const int64_t local = tile - tile_start[lo];
+        Counts cnt;
+        T smax = T(0);
+        if constexpr (D == 0) {
+            const int64_t wave = local * (blockDim.x >> 6) + (threadIdx.x >> 6);
+            sweep_x_wave<T, LIM, Eos>(a, eos, wave, threadIdx.x & 63, cnt, smax);
+        } else {
+            const int64_t nbx = (a.nlines + blockDim.x - 1) / blockDim.x;
+            const int64_t bx = local % nbx, by = local / nbx;
+            sweep_line<T, D, LIM, Eos, JET>(a, eos, bx * blockDim.x + threadIdx.x, (int)by * a.seg, cnt, smax);
+        }
+        flush_stats(a.stats, cnt, smax, a.mode == SW_FINAL && a.want_smax);
+    }
+}
+
+__global__ void k_advance_time(double* t, const double* dt, int ne)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ne) t[i] = t[i] + dt[i];
+}
+
+__global__ void k_fill_u32(unsigned int* p, int n, unsigned int v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -431,9 +503,9 @@ static hipError_t launch_axis(int lim, bool jet, dim3 grid, dim3 block, hipStrea
     }
 }
 
-template <typename T>
+template <typename T, class Eos>
 hipError_t launch_sweep(int axis, int lim, bool jet, dim3 grid, dim3 block, hipStream_t s,
-                        const SweepArgs<T>& a, const EosIdeal<T>& eos)
+                        const SweepArgs<T>& a, const Eos& eos)
 {
     switch (axis) {
     case 0: return launch_axis<T, 0>(lim, false, grid, block, s, a, eos);
@@ -443,11 +515,11 @@ hipError_t launch_sweep(int axis, int lim, bool jet, dim3 grid, dim3 block, hipS
     }
 }
 
-template <typename T>
-hipError_t launch_con2prim(int64_t n, hipStream_t s, const C2PArgs<T>& a, const EosIdeal<T>& eos)
+template <typename T, class Eos>
+hipError_t launch_con2prim(int64_t n, hipStream_t s, const C2PArgs<T>& a, const Eos& eos)
 {
     const int64_t nb = (n + 255) / 256;
-    hipLaunchKernelGGL((k_con2prim<T, EosIdeal<T>>), dim3((unsigned)nb), dim3(256), 0, s, a, eos);
+    hipLaunchKernelGGL((k_con2prim<T, Eos>), dim3((unsigned)nb), dim3(256), 0, s, a, eos);
     return hipGetLastError();
 }
 
@@ -468,14 +540,105 @@ hipError_t launch_fill_u64(hipStream_t s, unsigned long long* p, int64_t n, unsi
     return hipGetLastError();
 }
 
-template hipError_t launch_sweep<double>(int, int, bool, dim3, dim3, hipStream_t, const SweepArgs<double>&,
-                                         const EosIdeal<double>&);
-template hipError_t launch_sweep<float>(int, int, bool, dim3, dim3, hipStream_t, const SweepArgs<float>&,
-                                        const EosIdeal<float>&);
-template hipError_t launch_con2prim<double>(int64_t, hipStream_t, const C2PArgs<double>&,
-                                            const EosIdeal<double>&);
-template hipError_t launch_con2prim<float>(int64_t, hipStream_t, const C2PArgs<float>&,
-                                           const EosIdeal<float>&);
+
+template <typename T, int D, int LIM, class Eos, bool JET>
+static hipError_t launch_batch_lim(const SweepArgs<T>* tab, const int64_t* tile_start, int ne, unsigned int* counter,
+                                   int64_t total_tiles, int block, hipStream_t s, const Eos& eos)
+{
+    static int per_cu[3] = {0, 0, 0};  // resident blocks per CU, by block size 64/128/256
+    static int n_cu = 0;
+    const int bi = block == 64 ? 0 : (block == 128 ? 1 : 2);
+    if (per_cu[bi] == 0) {
+        int nb = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, reinterpret_cast<const void*>(&k_batch_sweep<T, D, LIM, Eos, JET>), block, 0);
+        if (e != hipSuccess) return e;
+        per_cu[bi] = nb > 0 ? nb : 1;
+        if (n_cu == 0) {
+            int dev = 0;
+            (void)hipGetDevice(&dev);
+            e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+            if (e != hipSuccess) return e;
+        }
+    }
+    const int64_t grid = std::min<int64_t>(total_tiles, (int64_t)per_cu[bi] * n_cu);
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_batch_sweep<T, D, LIM, Eos, JET>), dim3((unsigned)grid), dim3(block), 0, s, tab, tile_start,
+                       ne, counter, eos);
+    return hipGetLastError();
+}
+
+template <typename T, int D, class Eos>
+static hipError_t launch_batch_axis(int lim, bool jet, const SweepArgs<T>* tab, const int64_t* tile_start, int ne,
+                                    unsigned int* counter, int64_t total_tiles, int block, hipStream_t s,
+                                    const Eos& eos)
+{
+#define MF_BATCH_CASE(L)                                                                                      \
+    case L:                                                                                                  \
+        if constexpr (D == 2) {                                                                              \
+            if (jet) return launch_batch_lim<T, D, L, Eos, true>(tab, tile_start, ne, counter, total_tiles,    \
+                                                                 block, s, eos);                              \
+        }                                                                                                    \
+        return launch_batch_lim<T, D, L, Eos, false>(tab, tile_start, ne, counter, total_tiles, block, s, eos);
+    switch (lim) {
+        MF_BATCH_CASE(LIM_NONE)
+        MF_BATCH_CASE(LIM_MINMOD)
+        MF_BATCH_CASE(LIM_SUPERBEE)
+        MF_BATCH_CASE(LIM_MC)
+        MF_BATCH_CASE(LIM_VANLEER)
+        MF_BATCH_CASE(LIM_VANALBADA)
+    default: return hipErrorInvalidValue;
+    }
+#undef MF_BATCH_CASE
+}
+
+template <typename T, class Eos>
+hipError_t launch_batch_sweep(int axis, int lim, bool jet, const SweepArgs<T>* tab, const int64_t* tile_start, int ne,
+                              unsigned int* counter, int64_t total_tiles, int block, hipStream_t s, const Eos& eos)
+{
+    switch (axis) {
+    case 0: return launch_batch_axis<T, 0>(lim, false, tab, tile_start, ne, counter, total_tiles, block, s, eos);
+    case 1: return launch_batch_axis<T, 1>(lim, false, tab, tile_start, ne, counter, total_tiles, block, s, eos);
+    case 2: return launch_batch_axis<T, 2>(lim, jet, tab, tile_start, ne, counter, total_tiles, block, s, eos);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_advance_time(hipStream_t s, double* t, const double* dt, int ne)
+{
+    hipLaunchKernelGGL(k_advance_time, dim3((ne + 63) / 64), dim3(64), 0, s, t, dt, ne);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(hipStream_t s, unsigned int* p, int n, unsigned int v)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3((n + 63) / 64), dim3(64), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+template hipError_t launch_batch_sweep<double, EosIdeal<double>>(int, int, bool, const SweepArgs<double>*,
+                                                                 const int64_t*, int, unsigned int*, int64_t, int,
+                                                                 hipStream_t, const EosIdeal<double>&);
+template hipError_t launch_batch_sweep<float, EosIdeal<float>>(int, int, bool, const SweepArgs<float>*, const int64_t*,
+                                                               int, unsigned int*, int64_t, int, hipStream_t,
+                                                               const EosIdeal<float>&);
+template hipError_t launch_batch_sweep<double, EosTable>(int, int, bool, const SweepArgs<double>*, const int64_t*,
+                                                         int, unsigned int*, int64_t, int, hipStream_t,
+                                                         const EosTable&);
+
+template hipError_t launch_sweep<double, EosIdeal<double>>(int, int, bool, dim3, dim3, hipStream_t,
+                                                           const SweepArgs<double>&, const EosIdeal<double>&);
+template hipError_t launch_sweep<float, EosIdeal<float>>(int, int, bool, dim3, dim3, hipStream_t,
+                                                         const SweepArgs<float>&, const EosIdeal<float>&);
+template hipError_t launch_sweep<double, EosTable>(int, int, bool, dim3, dim3, hipStream_t,
+                                                   const SweepArgs<double>&, const EosTable&);
+template hipError_t launch_con2prim<double, EosIdeal<double>>(int64_t, hipStream_t, const C2PArgs<double>&,
+                                                              const EosIdeal<double>&);
+template hipError_t launch_con2prim<float, EosIdeal<float>>(int64_t, hipStream_t, const C2PArgs<float>&,
+                                                            const EosIdeal<float>&);
+template hipError_t launch_con2prim<double, EosTable>(int64_t, hipStream_t, const C2PArgs<double>&,
+                                                      const EosTable&);
 template hipError_t launch_totals<double>(hipStream_t, const TotalsArgs<double>&, int, double, double*);
 template hipError_t launch_totals<float>(hipStream_t, const TotalsArgs<float>&, int, double, double*);
 

@@ -9,17 +9,29 @@
 namespace mf {
 
 // One axis sweep of a Runge-Kutta stage; grid = (ceil(nlines / block), nseg).
-template <typename T>
+// Eos = EosIdeal<T> or (T = double) EosTable.
+template <typename T, class Eos>
 hipError_t launch_sweep(int axis, int lim, bool jet, dim3 grid, dim3 block, hipStream_t s,
-                        const SweepArgs<T>& a, const EosIdeal<T>& eos);
+                        const SweepArgs<T>& a, const Eos& eos);
 
-template <typename T>
-hipError_t launch_con2prim(int64_t n, hipStream_t s, const C2PArgs<T>& a, const EosIdeal<T>& eos);
+template <typename T, class Eos>
+hipError_t launch_con2prim(int64_t n, hipStream_t s, const C2PArgs<T>& a, const Eos& eos);
 
 // Deterministic sums of the four components over a.n cells, times dV, into out[4] (device).
 template <typename T>
 hipError_t launch_totals(hipStream_t s, const TotalsArgs<T>& a, int nblocks, double dV, double* out);
 
 hipError_t launch_fill_u64(hipStream_t s, unsigned long long* p, int64_t n, unsigned long long v);
+hipError_t launch_fill_u32(hipStream_t s, unsigned int* p, int n, unsigned int v);
+
+// One batched axis sweep: a persistent grid (resident blocks of the device)
+// draining the tile queue described by tab (one SweepArgs per event) and
+// tile_start (ne + 1 prefix offsets); *counter must be 0.
+template <typename T, class Eos>
+hipError_t launch_batch_sweep(int axis, int lim, bool jet, const SweepArgs<T>* tab, const int64_t* tile_start, int ne,
+                              unsigned int* counter, int64_t total_tiles, int block, hipStream_t s, const Eos& eos);
+
+// t[i] += dt[i], i < ne (device event times of batched stepping).
+hipError_t launch_advance_time(hipStream_t s, double* t, const double* dt, int ne);
 
 }  // namespace mf

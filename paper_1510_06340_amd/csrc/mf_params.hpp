@@ -50,7 +50,9 @@ template <typename T> struct SweepArgs {
     AxisConst<T> ac;
     T dt;
     // moving point-jet source (SW_FINAL only)
-    double jet_pos[3];    // jet position at the stage time
+    double jet_pos[3];    // jet position at the stage time (t_ptr == nullptr), else at t = 0
+    const double* t_ptr;  // batched stepping: device event time; the stage time is *t_ptr + t_off
+    double t_off;
     double jet_ve;        // v dE/dx
     double jet_v;         // v
     double jet_norm;      // (2 pi sigma^2)^(-3/2)
@@ -74,15 +76,5 @@ template <typename T> struct TotalsArgs {
     double* partial;    // 4 per block
 };
 
-// Monotone cubic table EoS (device pointers).
-struct TableArgs {
-    const double* e;    // nodes
-    const double* p;    // values
-    const double* m;    // node slopes
-    int32_t n;
-    int32_t log_uniform;  // nodes are log-uniform: index from log
-    double log_e0;        // ln e[0]
-    double inv_dlog;      // (n - 1) / (ln e[n-1] - ln e[0])
-};
 
 }  // namespace mf

@@ -56,6 +56,8 @@ struct mf_grid_s {
     hipStream_t stream = nullptr;
     int eos_kind = -1;
     double cs2 = 1.0 / 3.0;
+    EosTable table{};               // device view of the tabulated EoS
+    void* table_dev = nullptr;      // its records (library-owned)
     int seg_override[3] = {0, 0, 0};
     int block = 256;
     unsigned long long* dstats = nullptr;  // (n_events + 1) * ST_WORDS; the last slot is scratch
@@ -71,8 +73,32 @@ struct mf_grid_s {
     std::vector<Timed> timed;       // launches recorded since the last read
     std::vector<hipEvent_t> pool;   // recycled events
 
+    // batched stepping (mf_batch_step): tuned shapes, device tables, captured step
+    struct Batch {
+        bool tuned = false;
+        int shape[3] = {0, 0, 0};   // x: chunks per wavefront; y, z: cells per thread
+        int block[3] = {256, 256, 256};
+        std::vector<double> dt;     // the dt set the tables and the graph were built for
+        void* tab = nullptr;        // SweepArgs[nstage][3][ne]
+        int64_t* tiles = nullptr;   // [3][ne + 1] tile prefix per axis
+        int64_t total[3] = {0, 0, 0};
+        unsigned int* counters = nullptr;  // one per (stage, axis)
+        double* t_dev = nullptr;    // event times
+        double* dt_dev = nullptr;
+        std::vector<double> t_host; // staging for the time upload
+        hipStream_t stream = nullptr;
+        hipEvent_t ev_in = nullptr, ev_out = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipGraph_t graph = nullptr;
+    } batch;
+
     ~mf_grid_s()
     {
+        if (batch.exec) (void)hipGraphExecDestroy(batch.exec);
+        if (batch.graph) (void)hipGraphDestroy(batch.graph);
+        if (batch.ev_in) (void)hipEventDestroy(batch.ev_in);
+        if (batch.ev_out) (void)hipEventDestroy(batch.ev_out);
+        if (batch.stream) (void)hipStreamDestroy(batch.stream);
         for (auto& t : timed) {
             (void)hipEventDestroy(t.start);
             (void)hipEventDestroy(t.stop);
@@ -159,59 +185,88 @@ void set_axis_const(AxisConst<T>& ac, double dt, double dx, double alpha)
     ac.inv_dx = (T)(1.0 / dx);
 }
 
+// Argument block of one axis sweep d of one Runge-Kutta stage of event ev.
+// seg: cells per thread (y, z) or chunks of 64 row items per wavefront (x).
 template <typename T>
-int run_stage(mf_grid_s* g, Event& ev, unsigned long long* stats, void* const uin[4], void* const u0[4],
-              void* const out[4], int kind, double dt, double ts, bool want_smax)
+SweepArgs<T> make_sweep_args(const Event& ev, int d, int seg, unsigned long long* stats, void* const uin[4],
+                             void* const u0[4], void* const out[4], int kind, double dt, bool want_smax)
 {
-    const EosIdeal<T> eos = EosIdeal<T>::make(g->cs2);
+    const AxisGeom geo = axis_geom(ev.d.n, d);
+    SweepArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    for (int c = 0; c < 4; c++) {
+        a.u[c] = (const T*)uin[c];
+        a.L[c] = (T*)ev.L[c];
+        a.u0[c] = (const T*)u0[c];
+        a.out[c] = (T*)out[c];
+    }
+    a.nlines = geo.nlines;
+    a.stride_d = geo.stride_d;
+    a.stride_f = geo.stride_f;
+    a.stride_s = geo.stride_s;
+    a.N = geo.N;
+    a.n_fast = geo.n_fast;
+    a.seg = seg;
+    a.periodic = ev.d.bc[d] == MF_BC_PERIODIC;
+    a.k = ev.d.musta_k;
+    a.mode = d == 0 ? SW_WRITE : (d == 1 ? SW_ACCUM : SW_FINAL);
+    a.kind = kind;
+    a.want_smax = want_smax ? 1 : 0;
+    a.axis_f = geo.axis_f;
+    a.axis_s = geo.axis_s;
+    set_axis_const(a.ac, dt, ev.d.dx[d], ev.d.alpha);
+    a.dt = (T)dt;
+    if (ev.jet && d == 2) {
+        a.jet_pos[0] = ev.jet_x0[0];
+        a.jet_pos[1] = ev.jet_x0[1];
+        a.jet_pos[2] = ev.jet_x0[2];
+        a.jet_ve = ev.jet_v * ev.jet_dedx;
+        a.jet_v = ev.jet_v;
+        a.jet_norm = std::pow(2.0 * M_PI * ev.jet_sigma * ev.jet_sigma, -1.5);
+        a.jet_inv2s2 = 1.0 / (2.0 * ev.jet_sigma * ev.jet_sigma);
+    }
+    for (int q = 0; q < 3; q++) {
+        a.origin[q] = ev.d.origin[q];
+        a.dx[q] = ev.d.dx[q];
+    }
+    a.stats = stats;
+    return a;
+}
+
+// Tiles (blocks of the per-event kernels) of axis d at the given shape.
+int64_t axis_tiles(const Event& ev, int d, int seg, int block)
+{
+    const AxisGeom geo = axis_geom(ev.d.n, d);
+    if (d == 0) {
+        const int64_t items = geo.nlines * ((int64_t)geo.N + 2);
+        const int64_t waves = (items + 64LL * seg - 1) / (64LL * seg);
+        return (waves * 64 + block - 1) / block;
+    }
+    const int64_t nseg = (geo.N + seg - 1) / seg;
+    return ((geo.nlines + block - 1) / block) * nseg;
+}
+
+int default_shape(const Event& ev, int d)
+{
+    const AxisGeom geo = axis_geom(ev.d.n, d);
+    return d == 0 ? auto_chunks_x(geo) : auto_seg(geo);
+}
+
+template <typename T, class Eos>
+int run_stage(mf_grid_s* g, const Eos& eos, Event& ev, unsigned long long* stats, void* const uin[4],
+              void* const u0[4], void* const out[4], int kind, double dt, double ts, bool want_smax)
+{
     for (int d = 0; d < 3; d++) {
         const AxisGeom geo = axis_geom(ev.d.n, d);
-        SweepArgs<T> a;
-        std::memset(&a, 0, sizeof(a));
-        for (int c = 0; c < 4; c++) {
-            a.u[c] = (const T*)uin[c];
-            a.L[c] = (T*)ev.L[c];
-            a.u0[c] = (const T*)u0[c];
-            a.out[c] = (T*)out[c];
-        }
-        a.nlines = geo.nlines;
-        a.stride_d = geo.stride_d;
-        a.stride_f = geo.stride_f;
-        a.stride_s = geo.stride_s;
-        a.N = geo.N;
-        a.n_fast = geo.n_fast;
-        if (d == 0) a.seg = g->seg_override[0] > 0 ? g->seg_override[0] : auto_chunks_x(geo);
-        else a.seg = g->seg_override[d] > 0 ? std::min(g->seg_override[d], geo.N) : auto_seg(geo);
-        a.periodic = ev.d.bc[d] == MF_BC_PERIODIC;
-        a.k = ev.d.musta_k;
-        a.mode = d == 0 ? SW_WRITE : (d == 1 ? SW_ACCUM : SW_FINAL);
-        a.kind = kind;
-        a.want_smax = want_smax ? 1 : 0;
-        a.axis_f = geo.axis_f;
-        a.axis_s = geo.axis_s;
-        set_axis_const(a.ac, dt, ev.d.dx[d], ev.d.alpha);
-        a.dt = (T)dt;
+        int seg = g->seg_override[d] > 0 ? g->seg_override[d] : default_shape(ev, d);
+        if (d > 0) seg = std::min(seg, geo.N);
+        SweepArgs<T> a = make_sweep_args<T>(ev, d, seg, stats, uin, u0, out, kind, dt, want_smax);
         const bool jet = ev.jet && d == 2;
-        if (jet) {
-            a.jet_pos[0] = ev.jet_x0[0] + ev.jet_v * ts;
-            a.jet_pos[1] = ev.jet_x0[1];
-            a.jet_pos[2] = ev.jet_x0[2];
-            a.jet_ve = ev.jet_v * ev.jet_dedx;
-            a.jet_v = ev.jet_v;
-            a.jet_norm = std::pow(2.0 * M_PI * ev.jet_sigma * ev.jet_sigma, -1.5);
-            a.jet_inv2s2 = 1.0 / (2.0 * ev.jet_sigma * ev.jet_sigma);
-        }
-        for (int q = 0; q < 3; q++) {
-            a.origin[q] = ev.d.origin[q];
-            a.dx[q] = ev.d.dx[q];
-        }
-        a.stats = stats;
+        if (jet) a.jet_pos[0] = ev.jet_x0[0] + ev.jet_v * ts;
         dim3 block(g->block);
         dim3 grid;
         if (d == 0) {
-            const int64_t items = geo.nlines * ((int64_t)geo.N + 2);
-            const int64_t waves = (items + 64LL * a.seg - 1) / (64LL * a.seg);
-            grid = dim3((unsigned)((waves * 64 + g->block - 1) / g->block), 1);
+            grid = dim3((unsigned)axis_tiles(ev, 0, a.seg, g->block), 1);
         } else {
             const int64_t nseg = (geo.N + a.seg - 1) / a.seg;
             grid = dim3((unsigned)((geo.nlines + g->block - 1) / g->block), (unsigned)nseg);
@@ -222,7 +277,7 @@ int run_stage(mf_grid_s* g, Event& ev, unsigned long long* stats, void* const ui
             MF_HIP(g->take_event(&tm.stop));
             MF_HIP(hipEventRecord(tm.start, g->stream));
         }
-        hipError_t e = launch_sweep<T>(d, ev.d.limiter, jet, grid, block, g->stream, a, eos);
+        hipError_t e = launch_sweep<T, Eos>(d, ev.d.limiter, jet, grid, block, g->stream, a, eos);
         if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("sweep launch: ") + hipGetErrorString(e));
         if (g->profiling) {
             MF_HIP(hipEventRecord(tm.stop, g->stream));
@@ -232,24 +287,64 @@ int run_stage(mf_grid_s* g, Event& ev, unsigned long long* stats, void* const ui
     return MF_OK;
 }
 
-template <typename T>
-int run_steps(mf_grid_s* g, Event& ev, unsigned long long* stats, double dt, int nsteps)
+template <typename T, class Eos>
+int run_steps_eos(mf_grid_s* g, const Eos& eos, Event& ev, unsigned long long* stats, double dt, int nsteps)
 {
     int rc;
     for (int s = 0; s < nsteps; s++) {
         const double t = ev.t;
         if (ev.d.rk_order == 3) {
-            if ((rc = run_stage<T>(g, ev, stats, ev.U, ev.U, ev.U1, RK_FIRST, dt, t, false))) return rc;
-            if ((rc = run_stage<T>(g, ev, stats, ev.U1, ev.U, ev.U2, RK3_MID, dt, t + dt, false))) return rc;
-            if ((rc = run_stage<T>(g, ev, stats, ev.U2, ev.U, ev.U, RK3_LAST, dt, t + 0.5 * dt, true))) return rc;
+            if ((rc = run_stage<T>(g, eos, ev, stats, ev.U, ev.U, ev.U1, RK_FIRST, dt, t, false))) return rc;
+            if ((rc = run_stage<T>(g, eos, ev, stats, ev.U1, ev.U, ev.U2, RK3_MID, dt, t + dt, false))) return rc;
+            if ((rc = run_stage<T>(g, eos, ev, stats, ev.U2, ev.U, ev.U, RK3_LAST, dt, t + 0.5 * dt, true)))
+                return rc;
         } else {
-            if ((rc = run_stage<T>(g, ev, stats, ev.U, ev.U, ev.U1, RK_FIRST, dt, t, false))) return rc;
-            if ((rc = run_stage<T>(g, ev, stats, ev.U1, ev.U, ev.U, RK2_LAST, dt, t + dt, true))) return rc;
+            if ((rc = run_stage<T>(g, eos, ev, stats, ev.U, ev.U, ev.U1, RK_FIRST, dt, t, false))) return rc;
+            if ((rc = run_stage<T>(g, eos, ev, stats, ev.U1, ev.U, ev.U, RK2_LAST, dt, t + dt, true))) return rc;
         }
         ev.steps++;
         ev.t = ev.t + dt;
     }
     return MF_OK;
+}
+
+int run_steps(mf_grid_s* g, Event& ev, unsigned long long* stats, double dt, int nsteps)
+{
+    if (g->eos_kind == MF_EOS_TABLE) return run_steps_eos<double>(g, g->table, ev, stats, dt, nsteps);
+    if (ev.d.dtype == MF_F32) return run_steps_eos<float>(g, EosIdeal<float>::make(g->cs2), ev, stats, dt, nsteps);
+    return run_steps_eos<double>(g, EosIdeal<double>::make(g->cs2), ev, stats, dt, nsteps);
+}
+
+// Monotone piecewise-cubic node slopes (Fritsch & Carlson 1980), interior
+// slopes the weighted harmonic mean of Fritsch & Butland (1984), end slopes
+// from the one-sided three-point formula with the monotonicity clamp.
+void monotone_slopes(int n, const double* x, const double* y, std::vector<double>& m)
+{
+    m.assign(n, 0.0);
+    std::vector<double> h(n - 1), del(n - 1);
+    for (int i = 0; i + 1 < n; i++) {
+        h[i] = x[i + 1] - x[i];
+        del[i] = (y[i + 1] - y[i]) / h[i];
+    }
+    if (n == 2) {
+        m[0] = m[1] = del[0];
+        return;
+    }
+    for (int i = 1; i + 1 < n; i++) {
+        const bool same = (del[i - 1] > 0.0 && del[i] > 0.0) || (del[i - 1] < 0.0 && del[i] < 0.0);
+        if (!same) continue;
+        const double w1 = 2.0 * h[i] + h[i - 1];
+        const double w2 = h[i] + 2.0 * h[i - 1];
+        m[i] = (w1 + w2) / (w1 / del[i - 1] + w2 / del[i]);
+    }
+    auto end_slope = [](double h0, double h1, double d0, double d1) {
+        double sl = ((2.0 * h0 + h1) * d0 - h0 * d1) / (h0 + h1);
+        if (sl == 0.0 || d0 == 0.0 || (sl > 0.0) != (d0 > 0.0)) return 0.0;
+        if ((d0 > 0.0) != (d1 > 0.0) && std::fabs(sl) > std::fabs(3.0 * d0)) return 3.0 * d0;
+        return sl;
+    };
+    m[0] = end_slope(h[0], h[1], del[0], del[1]);
+    m[n - 1] = end_slope(h[n - 2], h[n - 3], del[n - 2], del[n - 3]);
 }
 
 template <typename T>
@@ -263,6 +358,226 @@ int enqueue_totals(mf_grid_s* g, const Event& ev, double* out)
     hipError_t e = launch_totals<T>(g->stream, a, kTotalsBlocks, dV, out);
     if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("totals launch: ") + hipGetErrorString(e));
     return MF_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Batched stepping: all events advance together, one persistent launch per
+// axis sweep and Runge-Kutta stage over a tile queue, the whole step captured
+// once into a HIP graph and replayed.
+// ---------------------------------------------------------------------------
+struct StageIO {
+    void* const* uin;
+    void* const* u0;
+    void* const* out;
+    int kind;
+    double t_off_frac;  // stage time = t + t_off_frac * dt
+    bool want_smax;
+};
+
+int stage_io(const Event& ev, int stage, StageIO& io)
+{
+    if (ev.d.rk_order == 3) {
+        if (stage == 0) io = {ev.U, ev.U, ev.U1, RK_FIRST, 0.0, false};
+        else if (stage == 1) io = {ev.U1, ev.U, ev.U2, RK3_MID, 1.0, false};
+        else io = {ev.U2, ev.U, ev.U, RK3_LAST, 0.5, true};
+    } else {
+        if (stage == 0) io = {ev.U, ev.U, ev.U1, RK_FIRST, 0.0, false};
+        else io = {ev.U1, ev.U, ev.U, RK2_LAST, 1.0, true};
+    }
+    return MF_OK;
+}
+
+// Host image of the batch tables for the given stages/axes and shapes.
+template <typename T>
+void build_tables(mf_grid_s* g, const double* dt, int nstage, const int shape[3], const int block[3],
+                  std::vector<SweepArgs<T>>& tab, std::vector<int64_t>& tiles, int64_t total[3])
+{
+    const int ne = (int)g->ev.size();
+    auto& b = g->batch;
+    tab.assign((size_t)nstage * 3 * ne, SweepArgs<T>());
+    tiles.assign((size_t)3 * (ne + 1), 0);
+    for (int d = 0; d < 3; d++) {
+        int64_t acc = 0;
+        for (int e = 0; e < ne; e++) {
+            const Event& ev = g->ev[e];
+            int seg = shape[d];
+            if (d > 0) seg = std::min(seg, ev.d.n[d]);
+            tiles[(size_t)d * (ne + 1) + e] = acc;
+            acc += axis_tiles(ev, d, seg, block[d]);
+            for (int st = 0; st < nstage; st++) {
+                StageIO io;
+                stage_io(ev, st, io);
+                SweepArgs<T> a = make_sweep_args<T>(ev, d, seg, g->dstats + (size_t)ST_WORDS * e, io.uin, io.u0,
+                                                    io.out, io.kind, dt[e], io.want_smax);
+                a.t_ptr = b.t_dev + e;
+                a.t_off = io.t_off_frac * dt[e];
+                tab[((size_t)st * 3 + d) * ne + e] = a;
+            }
+        }
+        tiles[(size_t)d * (ne + 1) + ne] = acc;
+        total[d] = acc;
+    }
+}
+
+int ensure_batch_buffers(mf_grid_s* g)
+{
+    auto& b = g->batch;
+    const int ne = (int)g->ev.size();
+    int rc = MF_OK;
+    if (!b.stream) MF_HIP(hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking));
+    if (!b.ev_in) MF_HIP(hipEventCreateWithFlags(&b.ev_in, hipEventDisableTiming));
+    if (!b.ev_out) MF_HIP(hipEventCreateWithFlags(&b.ev_out, hipEventDisableTiming));
+    if (!b.tab) rc = g->alloc(&b.tab, sizeof(SweepArgs<double>) * 3 * 3 * (size_t)ne);
+    if (!rc && !b.tiles) rc = g->alloc((void**)&b.tiles, sizeof(int64_t) * 3 * (size_t)(ne + 1));
+    if (!rc && !b.counters) rc = g->alloc((void**)&b.counters, sizeof(unsigned int) * 16);
+    if (!rc && !b.t_dev) rc = g->alloc((void**)&b.t_dev, sizeof(double) * (size_t)ne);
+    if (!rc && !b.dt_dev) rc = g->alloc((void**)&b.dt_dev, sizeof(double) * (size_t)ne);
+    return rc;
+}
+
+// Autotuner: for each axis, time the stage-1 sweep (which writes only
+// library-owned buffers: L and the stage state U1) over all events at every
+// candidate (block size, shape) and keep the fastest.
+template <typename T, class Eos>
+int batch_tune(mf_grid_s* g, const Eos& eos, const double* dt)
+{
+    auto& b = g->batch;
+    const int ne = (int)g->ev.size();
+    bool jet = false;
+    for (const Event& ev : g->ev) jet = jet || ev.jet;
+    const int lim = g->ev[0].d.limiter;
+    hipEvent_t t0, t1;
+    MF_HIP(hipEventCreate(&t0));
+    MF_HIP(hipEventCreate(&t1));
+    std::vector<double> tnow(ne);
+    for (int e = 0; e < ne; e++) tnow[e] = g->ev[e].t;
+    MF_HIP(hipMemcpyAsync(b.t_dev, tnow.data(), sizeof(double) * ne, hipMemcpyHostToDevice, b.stream));
+    const int cand_x[4] = {4, 8, 16, 32};
+    const int cand_yz[4] = {16, 32, 64, 128};
+    const int blocks[2] = {128, 256};
+    int best_shape[3] = {0, 0, 0}, best_block[3] = {256, 256, 256};
+    for (int d = 0; d < 3; d++) {
+        float best = 1e30f;
+        for (int bi = 0; bi < 2; bi++) {
+            for (int ci = 0; ci < 4; ci++) {
+                int shape[3] = {8, 64, 64}, block[3] = {256, 256, 256};
+                for (int q = 0; q < 3; q++) {
+                    shape[q] = best_shape[q] ? best_shape[q] : shape[q];
+                    block[q] = best_block[q];
+                }
+                shape[d] = d == 0 ? cand_x[ci] : cand_yz[ci];
+                block[d] = blocks[bi];
+                std::vector<SweepArgs<T>> tab;
+                std::vector<int64_t> tiles;
+                int64_t total[3];
+                build_tables<T>(g, dt, 1, shape, block, tab, tiles, total);
+                MF_HIP(hipMemcpyAsync(b.tab, tab.data(), sizeof(SweepArgs<T>) * tab.size(), hipMemcpyHostToDevice,
+                                      b.stream));
+                MF_HIP(hipMemcpyAsync(b.tiles, tiles.data(), sizeof(int64_t) * tiles.size(), hipMemcpyHostToDevice,
+                                      b.stream));
+                float ms = 0.0f;
+                for (int rep = 0; rep < 2; rep++) {
+                    hipError_t e = launch_fill_u32(b.stream, b.counters, 1, 0u);
+                    if (e != hipSuccess) return fail(MF_ERR_HIP, hipGetErrorString(e));
+                    MF_HIP(hipEventRecord(t0, b.stream));
+                    e = launch_batch_sweep<T, Eos>(d, lim, jet, (const SweepArgs<T>*)b.tab + (size_t)d * ne,
+                                                   b.tiles + (size_t)d * (ne + 1), ne, b.counters, total[d],
+                                                   block[d], b.stream, eos);
+                    if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("tuning launch: ") + hipGetErrorString(e));
+                    MF_HIP(hipEventRecord(t1, b.stream));
+                    MF_HIP(hipEventSynchronize(t1));
+                    MF_HIP(hipEventElapsedTime(&ms, t0, t1));
+                }
+                if (ms < best) {
+                    best = ms;
+                    best_shape[d] = shape[d];
+                    best_block[d] = block[d];
+                }
+            }
+        }
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    for (int q = 0; q < 3; q++) {
+        b.shape[q] = best_shape[q];
+        b.block[q] = best_block[q];
+    }
+    b.tuned = true;
+    return MF_OK;
+}
+
+template <typename T, class Eos>
+int batch_build(mf_grid_s* g, const Eos& eos, const double* dt)
+{
+    auto& b = g->batch;
+    const int ne = (int)g->ev.size();
+    const int nstage = g->ev[0].d.rk_order == 3 ? 3 : 2;
+    bool jet = false;
+    for (const Event& ev : g->ev) jet = jet || ev.jet;
+    const int lim = g->ev[0].d.limiter;
+    std::vector<SweepArgs<T>> tab;
+    std::vector<int64_t> tiles;
+    build_tables<T>(g, dt, nstage, b.shape, b.block, tab, tiles, b.total);
+    MF_HIP(hipMemcpyAsync(b.tab, tab.data(), sizeof(SweepArgs<T>) * tab.size(), hipMemcpyHostToDevice, b.stream));
+    MF_HIP(hipMemcpyAsync(b.tiles, tiles.data(), sizeof(int64_t) * tiles.size(), hipMemcpyHostToDevice, b.stream));
+    MF_HIP(hipMemcpyAsync(b.dt_dev, dt, sizeof(double) * ne, hipMemcpyHostToDevice, b.stream));
+    MF_HIP(hipStreamSynchronize(b.stream));
+    if (b.exec) {
+        (void)hipGraphExecDestroy(b.exec);
+        b.exec = nullptr;
+    }
+    if (b.graph) {
+        (void)hipGraphDestroy(b.graph);
+        b.graph = nullptr;
+    }
+    MF_HIP(hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = launch_fill_u32(b.stream, b.counters, nstage * 3, 0u);
+    for (int st = 0; st < nstage && e == hipSuccess; st++) {
+        for (int d = 0; d < 3 && e == hipSuccess; d++) {
+            e = launch_batch_sweep<T, Eos>(d, lim, jet, (const SweepArgs<T>*)b.tab + ((size_t)st * 3 + d) * ne,
+                                           b.tiles + (size_t)d * (ne + 1), ne, b.counters + st * 3 + d, b.total[d],
+                                           b.block[d], b.stream, eos);
+        }
+    }
+    if (e == hipSuccess) e = launch_advance_time(b.stream, b.t_dev, b.dt_dev, ne);
+    hipGraph_t graph = nullptr;
+    hipError_t ec = hipStreamEndCapture(b.stream, &graph);
+    if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("batched step capture: ") + hipGetErrorString(e));
+    if (ec != hipSuccess) return fail(MF_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+    b.graph = graph;
+    MF_HIP(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
+    b.dt.assign(dt, dt + ne);
+    return MF_OK;
+}
+
+template <typename T, class Eos>
+int batch_prepare(mf_grid_s* g, const Eos& eos, const double* dt)
+{
+    auto& b = g->batch;
+    const int ne = (int)g->ev.size();
+    int rc;
+    if (!b.tuned) {
+        if (g->seg_override[0] > 0 && g->seg_override[1] > 0 && g->seg_override[2] > 0) {
+            for (int q = 0; q < 3; q++) {
+                b.shape[q] = g->seg_override[q];
+                b.block[q] = g->block;
+            }
+            b.tuned = true;
+        } else if ((rc = batch_tune<T>(g, eos, dt))) {
+            return rc;
+        }
+    }
+    const bool same = b.exec && (int)b.dt.size() == ne && std::equal(b.dt.begin(), b.dt.end(), dt);
+    if (!same && (rc = batch_build<T>(g, eos, dt))) return rc;
+    return MF_OK;
+}
+
+int batch_prepare_any(mf_grid_s* g, const double* dt)
+{
+    if (g->eos_kind == MF_EOS_TABLE) return batch_prepare<double>(g, g->table, dt);
+    if (g->ev[0].d.dtype == MF_F32) return batch_prepare<float>(g, EosIdeal<float>::make(g->cs2), dt);
+    return batch_prepare<double>(g, EosIdeal<double>::make(g->cs2), dt);
 }
 
 int check_desc(const mf_grid_desc& d)
@@ -342,7 +657,6 @@ int mf_grid_free(mf_grid_t g)
 int mf_set_eos(mf_grid_t g, int32_t kind, double cs2, const double* e_tab, const double* p_tab, int32_t n_tab,
                const mf_surrogate* s)
 {
-    (void)e_tab; (void)p_tab; (void)n_tab;
     if (!g) return fail(MF_ERR_ARG, "null handle");
     if (kind == MF_EOS_IDEAL) {
         if (!(cs2 > 0.0 && cs2 < 1.0)) return fail(MF_ERR_ARG, "cs2 must be in (0, 1)");
@@ -351,8 +665,56 @@ int mf_set_eos(mf_grid_t g, int32_t kind, double cs2, const double* e_tab, const
         g->cs2 = cs2;
         return MF_OK;
     }
-    if (kind == MF_EOS_TABLE) return fail(MF_ERR_ARG, "table EoS not available in this build");
-    return fail(MF_ERR_ARG, "unknown EoS kind");
+    if (kind != MF_EOS_TABLE) return fail(MF_ERR_ARG, "unknown EoS kind");
+    if (!e_tab || !p_tab || n_tab < 3) return fail(MF_ERR_ARG, "table EoS needs n_tab >= 3 host nodes");
+    for (const Event& ev : g->ev)
+        if (ev.d.dtype != MF_F64) return fail(MF_ERR_ARG, "the table EoS runs in FP64 only");
+    for (int i = 0; i < n_tab; i++) {
+        if (!(e_tab[i] > 0.0) || !std::isfinite(e_tab[i]) || !(p_tab[i] >= 0.0) || !std::isfinite(p_tab[i]) ||
+            !(p_tab[i] < e_tab[i]))
+            return fail(MF_ERR_ARG, "table nodes need e > 0 and 0 <= p < e");
+        if (i > 0 && (!(e_tab[i] > e_tab[i - 1]) || p_tab[i] < p_tab[i - 1]))
+            return fail(MF_ERR_ARG, "table e must increase strictly and p must not decrease");
+    }
+    if (s) return fail(MF_ERR_ARG, "the learned seed is not available in this build");
+    std::vector<double> m;
+    monotone_slopes(n_tab, e_tab, p_tab, m);
+    std::vector<double> rec(4 * (size_t)n_tab);
+    for (int i = 0; i < n_tab; i++) {
+        rec[4 * i + 0] = e_tab[i];
+        rec[4 * i + 1] = p_tab[i];
+        rec[4 * i + 2] = m[i];
+        rec[4 * i + 3] = i + 1 < n_tab ? 1.0 / (e_tab[i + 1] - e_tab[i]) : 0.0;
+    }
+    // log-uniform nodes: the interval comes from log2(e) and a +-1 fix-up
+    const double l0 = std::log2(e_tab[0]), l1 = std::log2(e_tab[n_tab - 1]);
+    const double dl = (l1 - l0) / (n_tab - 1);
+    bool log_uniform = true;
+    for (int i = 0; i < n_tab && log_uniform; i++)
+        log_uniform = std::fabs(std::log2(e_tab[i]) - (l0 + i * dl)) <= 1e-6 * dl;
+    if (g->table_dev) {
+        MF_HIP(hipStreamSynchronize(g->stream));
+        (void)hipFree(g->table_dev);
+        g->allocs.erase(std::remove(g->allocs.begin(), g->allocs.end(), g->table_dev), g->allocs.end());
+        g->table_dev = nullptr;
+    }
+    int rc = g->alloc(&g->table_dev, rec.size() * sizeof(double));
+    if (rc) return rc;
+    MF_HIP(hipMemcpy(g->table_dev, rec.data(), rec.size() * sizeof(double), hipMemcpyHostToDevice));
+    EosTable& t = g->table;
+    t.rec = (const double4*)g->table_dev;
+    t.n = n_tab;
+    t.log_uniform = log_uniform ? 1 : 0;
+    t.lg0 = (float)l0;
+    t.inv_dlg = (float)(1.0 / dl);
+    t.e0 = e_tab[0];
+    t.p0_e0 = p_tab[0] / e_tab[0];
+    t.elast = e_tab[n_tab - 1];
+    t.plast = p_tab[n_tab - 1];
+    t.mlast = m[n_tab - 1];
+    t.max_iter = 100;
+    g->eos_kind = MF_EOS_TABLE;
+    return MF_OK;
 }
 
 int mf_set_source_jet(mf_grid_t g, int32_t event, const double x0[3], double v, double dEdx, double sigma)
@@ -419,7 +781,9 @@ int mf_set_tuning(mf_grid_t g, const int32_t seg[3], int32_t block)
     return MF_OK;
 }
 
-static int collect_stats(mf_grid_t g, double dt, mf_stats* st)
+static int check_strict(mf_grid_t g, const mf_stats* st);
+
+static int collect_stats(mf_grid_t g, const double* dts, mf_stats* st)
 {
     const int ne = (int)g->ev.size();
     for (int i = 0; i < ne; i++) {
@@ -444,7 +808,7 @@ static int collect_stats(mf_grid_t g, double dt, mf_stats* st)
         s.steps = ev.steps;
         s.smax = smax;
         const double dxmin = std::min(ev.d.dx[0], std::min(ev.d.dx[1], ev.d.dx[2]));
-        s.courant = smax * dt / dxmin;
+        s.courant = smax * dts[i] / dxmin;
         for (int c = 0; c < 4; c++) s.totals[c] = ht[4 * i + c];
         s.n_floor = (int64_t)w[ST_FLOOR];
         s.n_bad = (int64_t)w[ST_BAD];
@@ -466,8 +830,7 @@ int mf_step(mf_grid_t g, double dt, int32_t nsteps, mf_stats* st)
     for (int i = 0; i < ne; i++) {
         Event& ev = g->ev[i];
         unsigned long long* stats = g->dstats + (size_t)ST_WORDS * i;
-        int rc = ev.d.dtype == MF_F32 ? run_steps<float>(g, ev, stats, dt, nsteps)
-                                      : run_steps<double>(g, ev, stats, dt, nsteps);
+        int rc = run_steps(g, ev, stats, dt, nsteps);
         if (rc) return rc;
     }
     bool strict = false;
@@ -478,8 +841,15 @@ int mf_step(mf_grid_t g, double dt, int32_t nsteps, mf_stats* st)
         local.resize(ne);
         st = local.data();
     }
-    int rc = collect_stats(g, dt, st);
+    std::vector<double> dts(ne, dt);
+    int rc = collect_stats(g, dts.data(), st);
     if (rc) return rc;
+    return check_strict(g, st);
+}
+
+static int check_strict(mf_grid_t g, const mf_stats* st)
+{
+    const int ne = (int)g->ev.size();
     for (int i = 0; i < ne; i++) {
         if (!(g->ev[i].d.flags & MF_FLAG_STRICT)) continue;
         if (st[i].n_bad > 0 || st[i].n_floor > 0)
@@ -494,8 +864,47 @@ int mf_step(mf_grid_t g, double dt, int32_t nsteps, mf_stats* st)
 
 int mf_batch_step(mf_grid_t g, const double* dt, int32_t nsteps, mf_stats* st)
 {
-    (void)g; (void)dt; (void)nsteps; (void)st;
-    return fail(MF_ERR_STATE, "batched stepping not available in this build");
+    if (!g || !dt) return fail(MF_ERR_ARG, "null argument");
+    if (g->eos_kind < 0) return fail(MF_ERR_STATE, "no equation of state set");
+    if (nsteps < 0) return fail(MF_ERR_ARG, "nsteps must be >= 0");
+    const int ne = (int)g->ev.size();
+    for (int i = 0; i < ne; i++) {
+        if (!(dt[i] > 0.0) || !std::isfinite(dt[i])) return fail(MF_ERR_ARG, "dt must be finite and > 0");
+        const mf_grid_desc& d0 = g->ev[0].d;
+        const mf_grid_desc& di = g->ev[i].d;
+        if (di.dtype != d0.dtype || di.limiter != d0.limiter || di.rk_order != d0.rk_order)
+            return fail(MF_ERR_ARG, "batched events must share dtype, limiter and rk_order");
+    }
+    int rc = ensure_batch_buffers(g);
+    if (rc) return rc;
+    auto& b = g->batch;
+    // order after earlier work on the handle's stream
+    MF_HIP(hipEventRecord(b.ev_in, g->stream));
+    MF_HIP(hipStreamWaitEvent(b.stream, b.ev_in, 0));
+    if ((rc = batch_prepare_any(g, dt))) return rc;
+    b.t_host.resize(ne);
+    for (int i = 0; i < ne; i++) b.t_host[i] = g->ev[i].t;
+    MF_HIP(hipMemcpyAsync(b.t_dev, b.t_host.data(), sizeof(double) * ne, hipMemcpyHostToDevice, b.stream));
+    hipError_t e = launch_fill_u64(b.stream, g->dstats, (int64_t)ST_WORDS * ne, 0ULL);
+    if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("stats reset: ") + hipGetErrorString(e));
+    for (int s = 0; s < nsteps; s++) MF_HIP(hipGraphLaunch(b.exec, b.stream));
+    MF_HIP(hipEventRecord(b.ev_out, b.stream));
+    MF_HIP(hipStreamWaitEvent(g->stream, b.ev_out, 0));
+    for (int i = 0; i < ne; i++) {
+        Event& ev = g->ev[i];
+        for (int s = 0; s < nsteps; s++) ev.t = ev.t + dt[i];
+        ev.steps += nsteps;
+    }
+    bool strict = false;
+    for (const Event& ev : g->ev) strict = strict || (ev.d.flags & MF_FLAG_STRICT);
+    if (!st && !strict) return MF_OK;
+    std::vector<mf_stats> local;
+    if (!st) {
+        local.resize(ne);
+        st = local.data();
+    }
+    if ((rc = collect_stats(g, dt, st))) return rc;
+    return check_strict(g, st);
 }
 
 int mf_con2prim(mf_grid_t g, const void* const U[4], void* const prim[5], int64_t n, int32_t* iters_dev,
@@ -512,20 +921,26 @@ int mf_con2prim(mf_grid_t g, const void* const U[4], void* const prim[5], int64_
         if (!prim[c]) return fail(MF_ERR_ARG, "null output pointer");
     unsigned long long* stats = g->dstats + (size_t)ST_WORDS * g->ev.size();
     hipError_t e;
-    if (g->ev[0].d.dtype == MF_F32) {
+    if (g->eos_kind == MF_EOS_TABLE) {
+        C2PArgs<double> a;
+        for (int c = 0; c < 4; c++) a.U[c] = (const double*)U[c];
+        for (int c = 0; c < 5; c++) a.prim[c] = (double*)prim[c];
+        a.iters = iters_dev; a.n = n; a.stats = stats;
+        e = launch_con2prim<double, EosTable>(n, g->stream, a, g->table);
+    } else if (g->ev[0].d.dtype == MF_F32) {
         C2PArgs<float> a;
         for (int c = 0; c < 4; c++) a.U[c] = (const float*)U[c];
         for (int c = 0; c < 5; c++) a.prim[c] = (float*)prim[c];
         a.iters = iters_dev; a.n = n; a.stats = stats;
         const EosIdeal<float> eos = EosIdeal<float>::make(g->cs2);
-        e = launch_con2prim<float>(n, g->stream, a, eos);
+        e = launch_con2prim<float, EosIdeal<float>>(n, g->stream, a, eos);
     } else {
         C2PArgs<double> a;
         for (int c = 0; c < 4; c++) a.U[c] = (const double*)U[c];
         for (int c = 0; c < 5; c++) a.prim[c] = (double*)prim[c];
         a.iters = iters_dev; a.n = n; a.stats = stats;
         const EosIdeal<double> eos = EosIdeal<double>::make(g->cs2);
-        e = launch_con2prim<double>(n, g->stream, a, eos);
+        e = launch_con2prim<double, EosIdeal<double>>(n, g->stream, a, eos);
     }
     if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("con2prim launch: ") + hipGetErrorString(e));
     return MF_OK;

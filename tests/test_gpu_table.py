@@ -1,0 +1,88 @@
+"""GPU parity for the tabulated crossover EoS: con2prim and full steps vs the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1510_06340_amd import inputs as I
+from helpers import gpu_run, max_rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TABLE = I.crossover_table()
+
+
+def random_cons(rng, n, vmax=0.99):
+    from scipy.interpolate import PchipInterpolator
+    pf = PchipInterpolator(*TABLE)
+    e = np.exp(rng.uniform(math.log(2e-3), math.log(800.0), n))
+    d = rng.normal(size=(3, n))
+    d /= np.linalg.norm(d, axis=0)
+    v = d * vmax * rng.uniform(0, 1, n) ** 0.5
+    p = pf(e)
+    g2 = 1 / (1 - (v ** 2).sum(0))
+    return np.concatenate([((e + p) * g2 - p)[None], ((e + p) * g2)[None] * v]).reshape(4, 1, 1, n)
+
+
+def test_table_con2prim_matches_oracle():
+    import torch
+    from paper_1510_06340_amd import mf
+    rng = np.random.default_rng(5)
+    n = 200_000
+    U = random_cons(rng, n)
+    # include states at rest (e = E exactly) and below / above the table range
+    U[0, 0, 0, :3] = [5e-4, 1.7, 2e3]
+    U[1:, 0, 0, :3] = 0.0
+    prim_o, _ = oracle.con2prim(oracle.Problem(table=TABLE), U)
+    dev = to_dev(U)
+    out = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(5)]
+    it = torch.zeros(n, dtype=torch.int32, device="cuda")
+    g = mf.Grid([mf.make_desc((n, 1, 1), (1, 1, 1), (0, 0, 0), (0, 0, 0))], [dev])
+    g.set_eos_table(*TABLE)
+    g.con2prim(dev, out, it)
+    torch.cuda.synchronize()
+    pg = np.stack([t.cpu().numpy() for t in out])
+    iters = it.cpu().numpy()
+    g.free()
+    po = prim_o.reshape(5, -1)
+    E = U[0].ravel()
+    assert np.all(np.abs(pg[:2] - po[:2]) <= 1e-13 * E)
+    np.testing.assert_allclose(pg[2:], po[2:], rtol=0, atol=1e-13)
+    assert np.array_equal(pg[0, :3], U[0, 0, 0, :3])     # at rest: e = E exactly, no iterations
+    assert np.all(iters[:3] == 0) and iters[3:].min() >= 1 and iters.max() < 100
+    assert 2.0 < iters[3:].mean() < 12.0
+
+
+def test_crossover_hotspots_parity_small():
+    w = I.crossover_workloads(n_events=1, n=40, steps=6)[0]
+    w.n = (40, 37, 35)
+    U = I.initial_state(w)
+    Ug, st = gpu_run(w, U, eos_table=TABLE)
+    Uo, sto = oracle.step(oracle.Problem.from_workload(w, table=TABLE), U, w.dt, w.steps)
+    assert max_rel_err(Ug, Uo) <= 1e-10
+    assert st["newton_iters"] > 0 and st["n_bad"] == 0 and st["n_floor"] == sto["n_floor"]
+    assert st["smax"] == pytest.approx(sto["smax"], rel=1e-9)
+
+
+@pytest.mark.parametrize("lim", [I.LIM_MINMOD, I.LIM_SUPERBEE, I.LIM_VANLEER])
+def test_crossover_other_limiters_rk3(lim):
+    rng = np.random.default_rng(lim)
+    n = (17, 15, 13)
+    U = np.zeros((4,) + n[::-1])
+    U[0] = np.exp(rng.uniform(-2, 4, size=n[::-1]))
+    U[1:] = rng.uniform(-0.3, 0.3, size=(3,) + n[::-1]) * U[0]
+    w = I.Workload("t", n, (0.1, 0.1, 0.1), (0, 0, 0), (1, 0, 1), lim, 2, 3, 0.02, 3, eos=I.EOS_TABLE)
+    Ug, _ = gpu_run(w, U, eos_table=TABLE)
+    Uo, _ = oracle.step(oracle.Problem.from_workload(w, table=TABLE), U, w.dt, w.steps)
+    assert max_rel_err(Ug, Uo) <= 1e-11
+
+
+def test_crossover_192_full_size_one_step():
+    """One full step of the 192^3 crossover event (seed 2000) at the size the bench runs."""
+    w = I.crossover_workloads(n_events=1)[0]
+    U = I.initial_state(w)
+    Ug, st = gpu_run(w, U, eos_table=TABLE, nsteps=1)
+    Uo, sto = oracle.step(oracle.Problem.from_workload(w, table=TABLE), U, w.dt, 1)
+    assert max_rel_err(Ug, Uo) <= 1e-10
+    assert st["n_bad"] == 0
