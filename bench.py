@@ -76,15 +76,117 @@ def cpu_baseline(w, U, budget_s: float):
     }
 
 
+def upload(U, tdt):
+    import numpy as np
+    import torch
+    return [torch.from_numpy(np.ascontiguousarray(U[c]).ravel()).to(device="cuda", dtype=tdt) for c in range(4)]
+
+
+def run_single(args, w, U, table=None, jet_x0=None):
+    """One grid through mf_step; returns (ms_total, per-axis kernel ms and launches, end stats)."""
+    import torch
+    from paper_1510_06340_amd import mf
+    tdt = torch.float64 if args.dtype == "f64" else torch.float32
+    dev = upload(U, tdt)
+    g = mf.Grid([mf.desc_from_workload(w, mf.MF_F64 if args.dtype == "f64" else mf.MF_F32)], [dev])
+    if table is None:
+        g.set_eos_ideal(w.cs2)
+    else:
+        g.set_eos_table(*table)
+    if jet_x0 is not None:
+        g.set_jet(0, jet_x0, w.jet["v"], w.jet["dedx"], w.jet["sigma"])
+    if args.seg is not None or args.block != 256:
+        g.set_tuning(args.seg or (0, 0, 0), args.block)
+    calibration_copy(args)
+    if args.warmup > 0:
+        g.step(w.dt, args.warmup, stats=False)
+    torch.cuda.synchronize()
+    g.set_profiling(True)
+    g.get_profile()  # reset
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    g.step(w.dt, args.steps, stats=False)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    kms, klaunch = g.get_profile()
+    g.set_profiling(False)
+    st = g.step(w.dt, 1, stats=True)[0]  # one more step for the end-of-run diagnostics
+    g.free()
+    return ms_total, kms, klaunch, st
+
+
+def run_events(args, ws, Us, batched, table=None):
+    """Many events: one batched handle (mf_batch_step) or one mf_step call per event in turn."""
+    import torch
+    from paper_1510_06340_amd import mf
+    devs = [upload(U, torch.float64) for U in Us]
+    g = None
+    if batched:
+        g = mf.Grid([mf.desc_from_workload(w) for w in ws], devs)
+        if table is None:
+            g.set_eos_ideal()
+        else:
+            g.set_eos_table(*table)
+    dts = [w.dt for w in ws]
+    per = []
+    if not batched:
+        for w, d in zip(ws, devs):
+            h = mf.Grid([mf.desc_from_workload(w)], [d])
+            if table is None:
+                h.set_eos_ideal()
+            else:
+                h.set_eos_table(*table)
+            per.append(h)
+
+    def advance(n):
+        if batched:
+            g.batch_step(dts, n, stats=False)
+        else:
+            for h, dt in zip(per, dts):
+                h.step(dt, n, stats=False)
+
+    advance(max(args.warmup, 1))  # includes the autotuner and graph capture for the batched form
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    advance(args.steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    st = g.batch_step(dts, 1) if batched else [h.step(dt, 1)[0] for h, dt in zip(per, dts)]
+    for h in per:
+        h.free()
+    if g is not None:
+        g.free()
+    return ms, st
+
+
+def calibration_copy(args):
+    import torch
+    if args.calib_copy_mb > 0:
+        nel = args.calib_copy_mb * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's own count)")
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--n", type=int, default=256, help="cells per axis of the hot-spot grid")
+    ap.add_argument("--workload", choices=["hotspot", "shock", "jet", "ensemble", "crossover"], default="hotspot")
+    ap.add_argument("--n", type=int, default=None, help="cells per axis (hotspot / jet)")
+    ap.add_argument("--events", type=int, default=None, help="events (ensemble / crossover)")
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time (0 = skip)")
-    ap.add_argument("--seg", type=int, nargs=3, default=None, help="cells per thread along x, y, z")
+    ap.add_argument("--seg", type=int, nargs=3, default=None, help="x chunks per wavefront, y and z cells per thread")
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before timing, copy this many MiB device-to-device (a kernel of known traffic "
@@ -96,58 +198,40 @@ def main(argv=None):
               "the multi-GPU layout is described in DESIGN.md", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
     from paper_1510_06340_amd import inputs as I
-    from paper_1510_06340_amd import mf
 
     torch.cuda.set_device(0)
-    w = I.hotspot_workload(n=args.n)
-    U = I.initial_state(w)
-    tdt = torch.float64 if args.dtype == "f64" else torch.float32
-    dev = [torch.from_numpy(np.ascontiguousarray(U[c]).ravel()).to(device="cuda", dtype=tdt) for c in range(4)]
-    desc = mf.desc_from_workload(w, mf.MF_F64 if args.dtype == "f64" else mf.MF_F32)
-    g = mf.Grid([desc], [dev])
-    g.set_eos_ideal(w.cs2)
-    if args.seg is not None or args.block != 256:
-        g.set_tuning(args.seg or (0, 0, 0), args.block)
-
-    if args.calib_copy_mb > 0:
-        nel = args.calib_copy_mb * (1 << 20) // 8
-        src = torch.ones(nel, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    if args.warmup > 0:
-        g.step(w.dt, args.warmup, stats=False)
-    torch.cuda.synchronize()
-    g.set_profiling(True)
-    g.get_profile()  # reset
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record()
-    g.step(w.dt, args.steps, stats=False)
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_total = e0.elapsed_time(e1)
-    kms, klaunch = g.get_profile()
-    g.set_profiling(False)
-    st = g.step(w.dt, 1, stats=True)[0]  # one more step for the end-of-run diagnostics
-    g.free()
-
     elem = 8 if args.dtype == "f64" else 4
-    cell_updates = w.cells * args.steps
-    value = cell_updates / (ms_total / 1e3)
+    peak = FP64_PEAK_TFLOPS if args.dtype == "f64" else FP32_PEAK_TFLOPS
+    if args.workload in ("ensemble", "crossover"):
+        return bench_events(args, I)
+
+    table = None
+    jet_x0 = None
+    if args.workload == "hotspot":
+        w = I.hotspot_workload(n=args.n or 256)
+        desc = (f"hotspot {w.n[0]}x{w.n[1]}x{w.n[2]} (40 seeded Gaussian hot spots, seed {w.seed}), p=e/3, "
+                f"MC limiter, k={w.k}, RK{w.rk}, dt={w.dt:g}, outflow")
+    elif args.workload == "jet":
+        w = I.jet_workload(n=args.n or 512)
+        jet_x0 = I.jet_start(w)
+        desc = (f"jet {w.n[0]}^3 hot spots (seed {w.seed}) + point jet v=0.999 dE/dx=5 sigma=0.3, superbee, "
+                f"k={w.k}, RK{w.rk}, dt={w.dt:g}")
+    else:
+        w = I.shock_workload()
+        desc = "shock tube 200x16x16, e=10|1, minmod, k=2, RK2, dt=0.03"
+    if args.steps is None:
+        args.steps = w.steps
+    U = I.initial_state(w)
+    ms_total, kms, klaunch, st = run_single(args, w, U, table, jet_x0)
+
+    value = w.cells * args.steps / (ms_total / 1e3)
     fl_axis = flops_per_cell_axis(w.k, w.limiter)
     n_launch = sum(klaunch)
     avg_launch_ms = sum(kms) / max(n_launch, 1)
     achieved_tflops = fl_axis * w.cells / (avg_launch_ms / 1e3) / 1e12
-    peak = FP64_PEAK_TFLOPS if args.dtype == "f64" else FP32_PEAK_TFLOPS
     hbm_bytes = bytes_per_cell_step(w.rk, elem)
     hbm_gbs = value * hbm_bytes / 1e9
     out = {
@@ -163,14 +247,9 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": args.dtype,
         "data": "synthetic",
-        "config": {
-            "workload": f"hotspot {w.n[0]}x{w.n[1]}x{w.n[2]} (40 seeded Gaussian hot spots, seed {w.seed}), "
-                        f"p=e/3, MC limiter, k={w.k}, RK{w.rk}, dt={w.dt:g}, outflow",
-            "cells": w.cells,
-            "wall_s": wall,
-        },
+        "config": {"workload": desc, "cells": w.cells},
         "roofline": {
-            "kernel": "k_sweep (x, y and z axis sweeps)",
+            "kernel": "k_sweep / k_sweep_x (x, y and z axis sweeps)",
             "bound": "alu",
             "achieved": achieved_tflops,
             "peak": peak,
@@ -190,8 +269,53 @@ def main(argv=None):
         },
         "end_state": {"smax": st["smax"], "n_floor": st["n_floor"], "n_bad": st["n_bad"], "E_total": st["totals"][0]},
     }
-    if args.cpu_budget > 0:
+    if args.cpu_budget > 0 and args.workload != "jet":
         out["cpu_baseline"] = cpu_baseline(w, U, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_events(args, I):
+    """Ensemble (64 uneven events, p = e/3) or crossover (32 x 192^3, tabulated EoS): batched vs per-event."""
+    if args.workload == "ensemble":
+        ws = I.ensemble_workloads(n_events=args.events or 64)
+        table = None
+        desc = "ensemble: 64 events, sizes per axis from {96..192}, hot spots (seeds 1000+j), MC, k=3, RK2, dt=0.03"
+    else:
+        ws = I.crossover_workloads(n_events=args.events or 32)
+        table = I.crossover_table()
+        desc = "crossover: 32 events of 192^3 (seeds 2000+j), tabulated crossover EoS, MC, k=3, RK2, dt=0.03"
+    if args.steps is None:
+        args.steps = ws[0].steps
+    Us = [I.initial_state(w) for w in ws]
+    cells = sum(w.cells for w in ws)
+    ms_b, st_b = run_events(args, ws, Us, batched=True, table=table)
+    ms_p, st_p = run_events(args, ws, Us, batched=False, table=table)
+    value = cells * args.steps / (ms_b / 1e3)
+    plain = cells * args.steps / (ms_p / 1e3)
+    fl_axis = flops_per_cell_axis(ws[0].k, ws[0].limiter)
+    achieved = 3 * 2 * fl_axis * cells * args.steps / (ms_b / 1e3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_b / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "cells": cells, "form": "batched (persistent tile queue, graph replay)"},
+        "plain_per_event": {"value": plain, "ms_per_step": ms_p / args.steps, "speedup_batched": value / plain},
+        "roofline": {"kernel": "k_batch_sweep (all sweeps of the step)", "bound": "alu", "achieved": achieved,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": None, "note": "whole-step average (graph replay, no per-launch events)"},
+        "end_state": {"n_floor": sum(s["n_floor"] for s in st_b), "n_bad": sum(s["n_bad"] for s in st_b),
+                      "newton_iters": sum(s["newton_iters"] for s in st_b)},
+    }
     print(json.dumps(out), flush=True)
     return 0
 

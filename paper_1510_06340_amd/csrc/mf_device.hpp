@@ -189,9 +189,9 @@ template <typename T> struct EosIdeal {
 // con2prim (Sec. 2.6): the fixed point v = |M| / (E + p(E - |M| v)) is the
 // root of g(e) = e - E + |M|^2 / (E + p(e)) on the bracket [E (1 - m^2), E],
 // m = |M| / E (g is increasing there for dp/de < 1).  Safeguarded Newton from
-// the bracket midpoint: a step that leaves the current bracket is replaced by
-// bisection; the bracket shrinks with the sign of g; stop when
-// |de| <= 1e-12 e.  FP64 only.
+// the bracket midpoint: stop when the Newton correction |de| <= 1e-12 e;
+// otherwise the bracket shrinks with the sign of g and a step that leaves it
+// is replaced by bisection.  FP64 only.
 // ---------------------------------------------------------------------------
 struct EosTable {
     static constexpr int kWaves = 2;
@@ -269,15 +269,20 @@ struct EosTable {
             eval(e, p, dp);
             const double iw = Math<double>::rcp(E + p);
             const double g = (e - E) + M2 * iw;
+            const double gp = 1.0 - M2 * dp * iw * iw;
+            const double de = g * Math<double>::rcp(gp);
+            double en = e - de;
+            cnt.iters++;
+            // converged: accept the (tiny) Newton correction before any bracket test,
+            // which could otherwise reject an iterate sitting on the bracket edge
+            if (fabs(de) <= 1e-12 * e) {
+                e = en;
+                break;
+            }
             if (g > 0.0) hi = e;
             else lo = e;
-            const double gp = 1.0 - M2 * dp * iw * iw;
-            double en = e - g * Math<double>::rcp(gp);
             if (!(en > lo && en < hi)) en = 0.5 * (lo + hi);
-            cnt.iters++;
-            const bool done = fabs(en - e) <= 1e-12 * en;
             e = en;
-            if (done) break;
         }
         return e;
     }
