@@ -56,7 +56,11 @@ enum mf_limiter {
     MF_LIM_VANALBADA = 5  /* xi(r) = (r^2 + r) / (r^2 + 1) */
 };
 enum mf_eos_kind { MF_EOS_IDEAL = 0, MF_EOS_TABLE = 1 };
-enum mf_c2p_mode { MF_C2P_PLAIN = 0, MF_C2P_SEEDED = 1 };
+enum mf_c2p_mode {
+    MF_C2P_PLAIN = 0,     /* bracketed Newton from the bracket midpoint (table) / closed form (ideal) */
+    MF_C2P_SEEDED = 1,    /* table EoS: guess from the learned seed network, evaluated on the matrix cores */
+    MF_C2P_CONFORMAL = 2  /* table EoS: guess from the p = e/3 closed form (a baseline for the seed) */
+};
 
 #define MF_FLAG_STRICT 1u  /* mf_step fails on unphysical states or alpha*Courant > 1 */
 
@@ -90,9 +94,11 @@ typedef struct {
 } mf_stats;
 
 /* Optional learned con2prim seed for MF_EOS_TABLE: a 2 -> H -> H -> 1 tanh
- * MLP on x = ((ln E - in_shift[0]) * in_scale[0], (|M|/E - in_shift[1]) * in_scale[1])
- * predicting ln e = out_scale * y + out_shift.  Weights row-major, host
- * pointers, copied by mf_set_eos and rounded to bfloat16 on the device. */
+ * MLP (H = 64) on x = ((ln E - in_shift[0]) * in_scale[0], (|M|/E - in_shift[1]) * in_scale[1])
+ * predicting ln e = out_scale * y + out_shift.  Weights row-major FP32 host
+ * arrays, copied by mf_set_eos and rounded to bfloat16 on the device.  The
+ * sweeps read the network's predictions from a (ln E, |M|/E) grid the network
+ * fills once per mf_set_eos; mf_con2prim(MF_C2P_SEEDED) evaluates it per state. */
 typedef struct {
     int32_t hidden;      /* H (multiple of 16, <= 256) */
     const float* w1;     /* H x 2 */
@@ -156,6 +162,29 @@ int mf_batch_step(mf_grid_t g, const double* dt, int32_t nsteps, mf_stats* st);
  * MF_C2P_PLAIN or MF_C2P_SEEDED (needs a surrogate).  Asynchronous. */
 int mf_con2prim(mf_grid_t g, const void* const U[4], void* const prim[5], int64_t n,
                 int32_t* iters_dev, int32_t mode);
+
+/* Counters of the last mf_con2prim call: out = (clamped |M|, bad states,
+ * root-finder iterations, seeded solves restarted plain).  Synchronous. */
+int mf_con2prim_stats(mf_grid_t g, int64_t out[4]);
+
+/* ---- the seed network's training kernels (BF16 matrix cores, FP32 accumulation)
+ * Parameters: MF_MLP_PARAMS FP32 values in device memory, laid out
+ * W1[64][2], b1[64], W2[64][64], b2[64], w3[64], b3 (row-major).  Inputs X are
+ * n x 2 FP32 (row-major), targets and outputs n FP32; all device pointers,
+ * asynchronous on 'stream' (hipStream_t or NULL). */
+#define MF_MLP_HIDDEN 64
+#define MF_MLP_PARAMS 4417
+/* Scratch (in floats) that mf_mlp_grad needs for n samples. */
+int64_t mf_mlp_workspace(int64_t n);
+/* y = MLP(X). */
+int mf_mlp_forward(const float* params, const float* X, int64_t n, float* y, void* stream);
+/* Gradient of mean((MLP(X) - t)^2) into grad[MF_MLP_PARAMS]; the loss into
+ * *loss (device, nullable).  work: mf_mlp_workspace(n) floats. */
+int mf_mlp_grad(const float* params, const float* X, const float* t, int64_t n, float* grad, float* loss,
+                float* work, int64_t work_floats, void* stream);
+/* One Adam step (step >= 1) on params with moments m, v (MF_MLP_PARAMS each). */
+int mf_mlp_adam(float* params, const float* grad, float* m, float* v, int32_t step, float lr, float beta1,
+                float beta2, float eps, void* stream);
 
 /* Sums of (E, Mx, My, Mz) * dV over one event's cells (deterministic order).
  * Synchronous. */

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmf.so")
-SOURCES = ["mf_kernels.hip", "mf_runtime.hip"]
+SOURCES = ["mf_kernels.hip", "mf_mlp.hip", "mf_runtime.hip"]
 ARCH = os.environ.get("MF_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -71,6 +71,7 @@ struct Counts {
     uint32_t floor_ = 0;  // |M| clamped
     uint32_t bad = 0;     // E <= 0 or non-finite
     uint32_t iters = 0;   // root-finder iterations (table EoS)
+    uint32_t fallback = 0; // seeded solves that restarted from the plain bracket
 };
 
 // ---------------------------------------------------------------------------
@@ -203,6 +204,12 @@ struct EosTable {
     double e0, p0_e0;    // first node and p_0 / e_0
     double elast, plast, mlast;
     int32_t max_iter;
+    // learned seed: predictions ln e of the MLP on a grid over (ln E, |M|/E),
+    // read by bilinear interpolation (the grid is filled by the MLP kernel)
+    const float* seed;   // [sg0][sg1] or nullptr (plain solve)
+    int32_t sg0, sg1;
+    float seed_lnE0, seed_inv_dlnE;  // grid origin and inverse spacing in ln E
+    int32_t max_newton;              // seeded Newton iterations before the plain restart
 
     __device__ __forceinline__ void eval(double e, double& p, double& dp) const
     {
@@ -287,9 +294,54 @@ struct EosTable {
         return e;
     }
 
+    // Seeded solve: unsafeguarded Newton from e0 for at most max_newton
+    // iterations; if e0 or an iterate leaves the bracket, or the run has not
+    // converged, restart the plain solve from the bracket midpoint.
+    __device__ __forceinline__ double solve_seeded(double E, double M2, double e0, int nmax, Counts& cnt) const
+    {
+        const double lo = E - M2 * Math<double>::rcp(E);
+        const double hi = E;
+        if (e0 > lo && e0 < hi) {
+            double e = e0;
+            for (int it = 0; it < nmax; it++) {
+                double p, dp;
+                eval(e, p, dp);
+                const double iw = Math<double>::rcp(E + p);
+                const double g = (e - E) + M2 * iw;
+                const double gp = 1.0 - M2 * dp * iw * iw;
+                const double de = g * Math<double>::rcp(gp);
+                const double en = e - de;
+                cnt.iters++;
+                if (fabs(de) <= 1e-12 * e) return en;
+                if (!(en > lo && en < hi)) break;
+                e = en;
+            }
+        }
+        cnt.fallback++;
+        return solve(E, M2, 0.5 * (lo + hi), cnt);
+    }
+
+    // Bilinear read of the seed grid at (ln E, m); returns e0 = exp(ln e).
+    __device__ __forceinline__ double seed_guess(double E, double M2) const
+    {
+        const float lnE = __builtin_amdgcn_logf((float)E) * 0.69314718f;
+        const float m = (float)(Math<double>::sqrt(M2) * Math<double>::rcp(E));
+        float u = (lnE - seed_lnE0) * seed_inv_dlnE;
+        float v = m * (float)(sg1 - 1);
+        u = fminf(fmaxf(u, 0.0f), (float)(sg0 - 1) - 1e-3f);
+        v = fminf(fmaxf(v, 0.0f), (float)(sg1 - 1) - 1e-3f);
+        const int i = (int)u, j = (int)v;
+        const float fu = u - (float)i, fv = v - (float)j;
+        const float* r0 = seed + (int64_t)i * sg1 + j;
+        const float* r1 = r0 + sg1;
+        const float y = (1.0f - fu) * ((1.0f - fv) * r0[0] + fv * r0[1]) + fu * ((1.0f - fv) * r1[0] + fv * r1[1]);
+        return (double)__expf(y);
+    }
+
     __device__ __forceinline__ double recover(double E, double M2, Counts& cnt) const
     {
         if (M2 == 0.0) return E;
+        if (seed) return solve_seeded(E, M2, seed_guess(E, M2), max_newton, cnt);
         const double lo = E - M2 * Math<double>::rcp(E);
         return solve(E, M2, 0.5 * (lo + E), cnt);
     }

@@ -37,6 +37,7 @@ __device__ __forceinline__ void add_counts(Counts& a, const Counts& b)
     a.floor_ += b.floor_;
     a.bad += b.bad;
     a.iters += b.iters;
+    a.fallback += b.fallback;
 }
 
 template <typename T>
@@ -62,12 +63,14 @@ __device__ __forceinline__ void flush_stats(unsigned long long* st, const Counts
     const uint32_t f = wave_sum(cnt.floor_);
     const uint32_t b = wave_sum(cnt.bad);
     const uint32_t it = wave_sum(cnt.iters);
+    const uint32_t fb = wave_sum(cnt.fallback);
     double sm = 0.0;
     if (want_smax) sm = (double)wave_max(smax);
     if ((threadIdx.x & 63) == 0) {
         if (f) atomicAdd(&st[ST_FLOOR], (unsigned long long)f);
         if (b) atomicAdd(&st[ST_BAD], (unsigned long long)b);
         if (it) atomicAdd(&st[ST_ITERS], (unsigned long long)it);
+        if (fb) atomicAdd(&st[ST_FALLBACK], (unsigned long long)fb);
         if (want_smax && sm > 0.0) atomicMax(&st[ST_SMAX], (unsigned long long)__double_as_longlong(sm));
     }
 }

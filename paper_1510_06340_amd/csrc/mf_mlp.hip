@@ -1,0 +1,419 @@
+// mf_mlp.hip -- the learned con2prim seed: a 2 -> 64 -> 64 -> 1 tanh MLP on
+// gfx950 with bfloat16 weights and FP32 accumulation.
+//
+// The 64 x 64 hidden layer runs on the matrix cores
+// (v_mfma_f32_16x16x16_bf16: A 16x16 (M x K), B 16x16 (K x N), each lane
+// holding 4 consecutive K values; lane l holds A[l % 16][4 (l / 16) + i] and
+// B[4 (l / 16) + i][l % 16]; the accumulator holds D[4 (l / 16) + i][l % 16]).
+// One wavefront owns 64 samples (4 M-tiles); layers 1 and 3 (K = 2, N = 1)
+// run on the vector ALUs.
+//
+// Rounding points (the CPU reference applies the same ones):
+//   z1 = bf(W1) x + b1, h1 = tanh z1, h1b = bf(h1)
+//   z2 = bf(W2) h1b + b2, h2 = tanh z2, y = bf(w3) . h2 + b3
+// Training (mean squared error) back-propagates through the same points,
+// with dz2 rounded to bf16 as the operand of both dW2 = dz2b^T h1b and
+// dh1 = dz2b bf(W2) on the matrix cores.
+//
+// Parameter block (FP32, contiguous): W1[64][2], b1[64], W2[64][64], b2[64],
+// w3[64], b3.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "mf_device.hpp"
+#include "mf_mlp.hpp"
+
+namespace mf {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int H = kMlpHidden;
+constexpr int OFF_W1 = 0;
+constexpr int OFF_B1 = OFF_W1 + 2 * H;
+constexpr int OFF_W2 = OFF_B1 + H;
+constexpr int OFF_B2 = OFF_W2 + H * H;
+constexpr int OFF_W3 = OFF_B2 + H;
+constexpr int OFF_B3 = OFF_W3 + H;
+static_assert(OFF_B3 + 1 == kMlpParams, "parameter layout");
+
+constexpr int LDA = H + 4;  // padded LDS row (bf16 elements)
+
+__device__ __forceinline__ unsigned short f2bf(float f)
+{
+    unsigned int u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
+    return (unsigned short)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
+
+__device__ __forceinline__ float bfr(float f) { return bf2f(f2bf(f)); }
+
+// Shared-memory image of the weights used by the matrix-core layer.
+struct MlpShared {
+    unsigned short w2[H * LDA];   // bf(W2)[n][k]
+    unsigned short w2t[H * LDA];  // bf(W2)[k][n] (transposed)
+    float w1[2 * H];              // bf(W1)
+    float b1[H];
+    float b2[H];
+    float w3[H];                  // bf(w3)
+    float b3;
+};
+
+__device__ void load_shared(const float* __restrict__ P, MlpShared& s)
+{
+    for (int i = threadIdx.x; i < H * H; i += blockDim.x) {
+        const int n = i / H, k = i % H;
+        const unsigned short v = f2bf(P[OFF_W2 + i]);
+        s.w2[n * LDA + k] = v;
+        s.w2t[k * LDA + n] = v;
+    }
+    for (int i = threadIdx.x; i < 2 * H; i += blockDim.x) s.w1[i] = bfr(P[OFF_W1 + i]);
+    for (int i = threadIdx.x; i < H; i += blockDim.x) {
+        s.b1[i] = P[OFF_B1 + i];
+        s.b2[i] = P[OFF_B2 + i];
+        s.w3[i] = bfr(P[OFF_W3 + i]);
+    }
+    if (threadIdx.x == 0) s.b3 = P[OFF_B3];
+}
+
+// Forward pass of one wavefront (64 samples, lane l owns sample l).
+// sA: this wavefront's [64][LDA] bf16 buffer.  Returns, in the matrix-core
+// accumulator layout, z2 (without bias) for the 4 x 4 (M, N) tiles, and y for
+// the samples 16 mt + 4 (l / 16) + i in yv[mt][i] (valid in every lane).
+__device__ __forceinline__ void mlp_forward_wave(const MlpShared& s, unsigned short* sA, float x0, float x1,
+                                                 f32x4 acc[4][4], float yv[4][4])
+{
+    const int l = threadIdx.x & 63;
+    // layer 1 (VALU): h1b of this lane's sample into row l of sA
+    for (int h = 0; h < H; h += 2) {
+        const float z0 = __builtin_fmaf(s.w1[2 * h], x0, __builtin_fmaf(s.w1[2 * h + 1], x1, 0.0f)) + s.b1[h];
+        const float z1 = __builtin_fmaf(s.w1[2 * h + 2], x0, __builtin_fmaf(s.w1[2 * h + 3], x1, 0.0f)) + s.b1[h + 1];
+        const unsigned int pk = (unsigned int)f2bf(tanhf(z0)) | ((unsigned int)f2bf(tanhf(z1)) << 16);
+        *(unsigned int*)&sA[l * LDA + h] = pk;
+    }
+    __syncthreads();
+    // layer 2 (matrix cores): z2[s][n] = sum_k h1b[s][k] bf(W2)[n][k]
+    const int r = l & 15, q = l >> 4;
+    for (int mt = 0; mt < 4; mt++) {
+        for (int nt = 0; nt < 4; nt++) acc[mt][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int kt = 0; kt < 4; kt++) {
+            const bf16x4 a = *(const bf16x4*)&sA[(mt * 16 + r) * LDA + kt * 16 + 4 * q];
+            for (int nt = 0; nt < 4; nt++) {
+                const bf16x4 b = *(const bf16x4*)&s.w2[(nt * 16 + r) * LDA + kt * 16 + 4 * q];
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[mt][nt], 0, 0, 0);
+            }
+        }
+    }
+    // layer 3 (VALU): y[s] = sum_n bf(w3)[n] tanh(z2[s][n] + b2[n]) + b3
+    for (int mt = 0; mt < 4; mt++) {
+        float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int nt = 0; nt < 4; nt++) {
+            const int n = nt * 16 + r;
+            for (int i = 0; i < 4; i++) part[i] = __builtin_fmaf(s.w3[n], tanhf(acc[mt][nt][i] + s.b2[n]), part[i]);
+        }
+        for (int i = 0; i < 4; i++) {
+            float v = part[i];
+            for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);  // sum over the 16 lanes of the row group
+            yv[mt][i] = v + s.b3;
+        }
+    }
+}
+
+// y = MLP(X) for B samples (X row-major B x 2).
+__global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ P, const float* __restrict__ X,
+                                                     int64_t B, float* __restrict__ y)
+{
+    __shared__ MlpShared s;
+    __shared__ unsigned short sA[4][64 * LDA];
+    load_shared(P, s);
+    __syncthreads();
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int64_t base = ((int64_t)blockIdx.x * 4 + w) * 64;
+    const int64_t smp = base + l;
+    const float x0 = smp < B ? X[2 * smp] : 0.0f;
+    const float x1 = smp < B ? X[2 * smp + 1] : 0.0f;
+    f32x4 acc[4][4];
+    float yv[4][4];
+    mlp_forward_wave(s, sA[w], x0, x1, acc, yv);
+    const int r = l & 15, q = l >> 4;
+    if (r == 0) {
+        for (int mt = 0; mt < 4; mt++)
+            for (int i = 0; i < 4; i++) {
+                const int64_t o = base + mt * 16 + 4 * q + i;
+                if (o < B) y[o] = yv[mt][i];
+            }
+    }
+}
+
+// Forward + backward of the mean squared error for B samples: one partial
+// gradient (kMlpParams floats, plus the partial squared-error sum) per
+// wavefront into part[wave][kMlpParams + 1].
+__global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ P, const float* __restrict__ X,
+                                                  const float* __restrict__ T, int64_t B, float* __restrict__ part)
+{
+    __shared__ MlpShared s;
+    __shared__ unsigned short sA[4][64 * LDA];   // h1b per wavefront
+    __shared__ unsigned short sD[4][64 * LDA];   // dz2b per wavefront ([s][n])
+    __shared__ float sX[4][64][2];
+    load_shared(P, s);
+    __syncthreads();
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int r = l & 15, q = l >> 4;
+    const int64_t base = ((int64_t)blockIdx.x * 4 + w) * 64;
+    const int64_t smp = base + l;
+    const bool valid = smp < B;
+    const float x0 = valid ? X[2 * smp] : 0.0f;
+    const float x1 = valid ? X[2 * smp + 1] : 0.0f;
+    sX[w][l][0] = x0;
+    sX[w][l][1] = x1;
+    f32x4 acc[4][4];
+    float yv[4][4];
+    mlp_forward_wave(s, sA[w], x0, x1, acc, yv);
+
+    // dy for the samples of this lane's accumulator rows; padding samples get 0
+    float dy[4][4];
+    float sq = 0.0f;
+    for (int mt = 0; mt < 4; mt++)
+        for (int i = 0; i < 4; i++) {
+            const int64_t o = base + mt * 16 + 4 * q + i;
+            const float d = o < B ? yv[mt][i] - T[o] : 0.0f;
+            dy[mt][i] = 2.0f * d / (float)B;
+            if (r == 0) sq += d * d;
+        }
+    // dz2 = dy w3b (1 - h2^2) in the accumulator layout; dw3, db2 partials per column n
+    float gw3[4] = {0, 0, 0, 0}, gb2[4] = {0, 0, 0, 0};
+    bf16x4 dzA[4][4];  // dz2b as the A operand of dW2 (rows n, columns s): same lane layout
+    for (int mt = 0; mt < 4; mt++)
+        for (int nt = 0; nt < 4; nt++) {
+            const int n = nt * 16 + r;
+            short v[4];
+            for (int i = 0; i < 4; i++) {
+                const float h2 = tanhf(acc[mt][nt][i] + s.b2[n]);
+                const float dz = dy[mt][i] * s.w3[n] * (1.0f - h2 * h2);
+                gw3[nt] = __builtin_fmaf(dy[mt][i], h2, gw3[nt]);
+                gb2[nt] += dz;
+                const unsigned short b = f2bf(dz);
+                v[i] = (short)b;
+                sD[w][(mt * 16 + 4 * q + i) * LDA + n] = b;
+            }
+            dzA[mt][nt] = bf16x4{v[0], v[1], v[2], v[3]};
+        }
+    __syncthreads();
+
+    float* out = part + ((int64_t)blockIdx.x * 4 + w) * (kMlpParams + 1);
+    // dW2[n][k] = sum_s dz2b[s][n] h1b[s][k]: A = dz2b^T (held in registers), B[s][k] = h1b from sA
+    for (int nt = 0; nt < 4; nt++)
+        for (int kt = 0; kt < 4; kt++) {
+            f32x4 g = {0.0f, 0.0f, 0.0f, 0.0f};
+            for (int mt = 0; mt < 4; mt++) {
+                short v[4];
+                for (int i = 0; i < 4; i++) v[i] = (short)sA[w][(mt * 16 + 4 * q + i) * LDA + kt * 16 + r];
+                const bf16x4 b = bf16x4{v[0], v[1], v[2], v[3]};
+                g = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(dzA[mt][nt], b, g, 0, 0, 0);
+            }
+            for (int i = 0; i < 4; i++) out[OFF_W2 + (nt * 16 + 4 * q + i) * H + kt * 16 + r] = g[i];
+        }
+    // dh1[s][k] = sum_n dz2b[s][n] bf(W2)[n][k]: A from sD (rows s), B[n][k] = w2t[k][n]
+    float gw1[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}}, gb1[4] = {0, 0, 0, 0};
+    for (int mt = 0; mt < 4; mt++)
+        for (int kt = 0; kt < 4; kt++) {
+            f32x4 g = {0.0f, 0.0f, 0.0f, 0.0f};
+            for (int nt = 0; nt < 4; nt++) {
+                const bf16x4 a = *(const bf16x4*)&sD[w][(mt * 16 + r) * LDA + nt * 16 + 4 * q];
+                const bf16x4 b = *(const bf16x4*)&s.w2t[(kt * 16 + r) * LDA + nt * 16 + 4 * q];
+                g = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, g, 0, 0, 0);
+            }
+            // dz1 = dh1 (1 - h1^2), with h1 recomputed from the sample's x (padding samples have dz2 = 0)
+            const int k = kt * 16 + r;
+            for (int i = 0; i < 4; i++) {
+                const int sl = mt * 16 + 4 * q + i;
+                const float xa = sX[w][sl][0], xb = sX[w][sl][1];
+                const float z1 = __builtin_fmaf(s.w1[2 * k], xa, __builtin_fmaf(s.w1[2 * k + 1], xb, 0.0f)) + s.b1[k];
+                const float h1 = tanhf(z1);
+                const float dz1 = g[i] * (1.0f - h1 * h1);
+                gw1[kt][0] = __builtin_fmaf(dz1, xa, gw1[kt][0]);
+                gw1[kt][1] = __builtin_fmaf(dz1, xb, gw1[kt][1]);
+                gb1[kt] += dz1;
+            }
+        }
+    // column sums over the 4 row groups (lanes r, r + 16, r + 32, r + 48)
+    for (int nt = 0; nt < 4; nt++) {
+        for (int o = 16; o < 64; o <<= 1) {
+            gw3[nt] += __shfl_xor(gw3[nt], o, 64);
+            gb2[nt] += __shfl_xor(gb2[nt], o, 64);
+            gw1[nt][0] += __shfl_xor(gw1[nt][0], o, 64);
+            gw1[nt][1] += __shfl_xor(gw1[nt][1], o, 64);
+            gb1[nt] += __shfl_xor(gb1[nt], o, 64);
+        }
+    }
+    for (int o = 1; o < 64; o <<= 1) sq += __shfl_xor(sq, o, 64);
+    if (q == 0) {
+        for (int nt = 0; nt < 4; nt++) {
+            const int n = nt * 16 + r;
+            out[OFF_W3 + n] = gw3[nt];
+            out[OFF_B2 + n] = gb2[nt];
+            out[OFF_W1 + 2 * n] = gw1[nt][0];
+            out[OFF_W1 + 2 * n + 1] = gw1[nt][1];
+            out[OFF_B1 + n] = gb1[nt];
+        }
+    }
+    // db3 = sum dy (one value per sample: lanes with r == 0 hold 16 samples each)
+    float db3 = 0.0f;
+    if (r == 0)
+        for (int mt = 0; mt < 4; mt++)
+            for (int i = 0; i < 4; i++) db3 += dy[mt][i];
+    for (int o = 1; o < 64; o <<= 1) db3 += __shfl_xor(db3, o, 64);
+    if (l == 0) {
+        out[OFF_B3] = db3;
+        out[kMlpParams] = sq;
+    }
+}
+
+// grad[p] = sum over wavefronts of part[w][p] (fixed order); loss = sum sq / B.
+__global__ void k_mlp_reduce(const float* __restrict__ part, int nwaves, int64_t B, float* __restrict__ grad,
+                             float* __restrict__ loss)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > kMlpParams) return;
+    float acc = 0.0f;
+    for (int w = 0; w < nwaves; w++) acc += part[(int64_t)w * (kMlpParams + 1) + p];
+    if (p < kMlpParams) grad[p] = acc;
+    else if (loss) *loss = acc / (float)B;
+}
+
+// Adam (Kingma & Ba 2015) on the FP32 master parameters.
+__global__ void k_mlp_adam(float* __restrict__ P, const float* __restrict__ g, float* __restrict__ m,
+                           float* __restrict__ v, int n, float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    P[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// Seeded con2prim over n states with the tabulated EoS.  mode 1: the initial
+// guess is exp(MLP(ln E, |M|/E)) evaluated on the matrix cores for the
+// wavefront's 64 states; mode 2: the conformal (p = e/3) closed form.  Then at
+// most max_newton unsafeguarded Newton steps, and the plain bracketed solve
+// if the guess or an iterate leaves the bracket or the steps do not converge.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_con2prim_seeded(C2PArgs<double> a, EosTable eos, const float* __restrict__ P,
+                                                         SeedNorm nrm, int mode)
+{
+    __shared__ MlpShared s;
+    __shared__ unsigned short sA[4][64 * LDA];
+    __shared__ float sy[4][64];
+    if (mode == 1) load_shared(P, s);
+    __syncthreads();
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < a.n;
+    double E = 1.0, Mx = 0.0, My = 0.0, Mz = 0.0;
+    if (valid) {
+        E = a.U[0][i]; Mx = a.U[1][i]; My = a.U[2][i]; Mz = a.U[3][i];
+    }
+    double M2 = Mx * Mx + My * My + Mz * Mz;
+    Counts cnt;
+    const bool ok = eos.fixup(E, Mx, My, Mz, M2, cnt);
+    if (!ok) {
+        E = 1.0; Mx = 0.0; My = 0.0; Mz = 0.0; M2 = 0.0;
+    }
+    float y = 0.0f;
+    if (mode == 1) {
+        const float x0 = (__builtin_amdgcn_logf((float)E) * 0.69314718f - nrm.in_shift[0]) * nrm.in_scale[0];
+        const float x1 = ((float)(sqrt(M2) / E) - nrm.in_shift[1]) * nrm.in_scale[1];
+        f32x4 acc[4][4];
+        float yv[4][4];
+        mlp_forward_wave(s, sA[w], x0, x1, acc, yv);
+        if ((l & 15) == 0)
+            for (int mt = 0; mt < 4; mt++)
+                for (int k = 0; k < 4; k++) sy[w][mt * 16 + 4 * (l >> 4) + k] = yv[mt][k];
+        __syncthreads();
+        y = sy[w][l];
+    }
+    double e = E;
+    if (M2 != 0.0) {
+        double e0;
+        if (mode == 1) {
+            e0 = exp((double)(y * nrm.out_scale + nrm.out_shift));
+        } else {
+            const double c = 1.0 / 3.0, q = 1.0 + c;
+            e0 = E - 2.0 * M2 / (q * E + sqrt(q * q * E * E - 4.0 * c * M2));
+        }
+        e = eos.solve_seeded(E, M2, e0, nrm.max_newton, cnt);
+    }
+    double p, dp;
+    eos.eval(e, p, dp);
+    const double iw = 1.0 / (E + p);
+    if (valid) {
+        if (ok) {
+            a.prim[0][i] = e; a.prim[1][i] = p;
+            a.prim[2][i] = Mx * iw; a.prim[3][i] = My * iw; a.prim[4][i] = Mz * iw;
+        } else {
+            a.prim[0][i] = 0.0; a.prim[1][i] = 0.0; a.prim[2][i] = 0.0; a.prim[3][i] = 0.0; a.prim[4][i] = 0.0;
+        }
+        if (a.iters) a.iters[i] = (int32_t)cnt.iters;
+    }
+    if (!valid) cnt = Counts();
+    // counters: one atomic per wavefront and counter
+    unsigned int c[4] = {cnt.floor_, cnt.bad, cnt.iters, cnt.fallback};
+    for (int k = 0; k < 4; k++)
+        for (int o = 32; o > 0; o >>= 1) c[k] += __shfl_xor(c[k], o, 64);
+    if (l == 0) {
+        if (c[0]) atomicAdd(&a.stats[ST_FLOOR], (unsigned long long)c[0]);
+        if (c[1]) atomicAdd(&a.stats[ST_BAD], (unsigned long long)c[1]);
+        if (c[2]) atomicAdd(&a.stats[ST_ITERS], (unsigned long long)c[2]);
+        if (c[3]) atomicAdd(&a.stats[ST_FALLBACK], (unsigned long long)c[3]);
+    }
+}
+
+hipError_t con2prim_seeded(int64_t n, hipStream_t s, const C2PArgs<double>& a, const EosTable& eos, const float* P,
+                           const SeedNorm& nrm, int mode)
+{
+    const int64_t nb = (n + 255) / 256;
+    hipLaunchKernelGGL(k_con2prim_seeded, dim3((unsigned)nb), dim3(256), 0, s, a, eos, P, nrm, mode);
+    return hipGetLastError();
+}
+
+hipError_t mlp_forward(const float* P, const float* X, int64_t B, float* y, hipStream_t s)
+{
+    if (B <= 0) return hipSuccess;
+    const int64_t blocks = (B + 255) / 256;
+    hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)blocks), dim3(256), 0, s, P, X, B, y);
+    return hipGetLastError();
+}
+
+int64_t mlp_grad_partials(int64_t B) { return ((B + 255) / 256) * 4; }
+
+hipError_t mlp_grad(const float* P, const float* X, const float* T, int64_t B, float* part, float* grad, float* loss,
+                    hipStream_t s)
+{
+    if (B <= 0) return hipErrorInvalidValue;
+    const int64_t blocks = (B + 255) / 256;
+    hipLaunchKernelGGL(k_mlp_grad, dim3((unsigned)blocks), dim3(256), 0, s, P, X, T, B, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((kMlpParams + 1 + 255) / 256), dim3(256), 0, s, part,
+                       (int)(blocks * 4), B, grad, loss);
+    return hipGetLastError();
+}
+
+hipError_t mlp_adam(float* P, const float* g, float* m, float* v, int step, float lr, float b1, float b2, float eps,
+                    hipStream_t s)
+{
+    const float c1 = 1.0f - powf(b1, (float)step);
+    const float c2 = 1.0f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, P, g, m, v, kMlpParams, lr, b1,
+                       b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+}  // namespace mf

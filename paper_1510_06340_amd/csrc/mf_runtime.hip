@@ -12,6 +12,7 @@
 
 #include "../../include/mf.h"
 #include "mf_kernels.hpp"
+#include "mf_mlp.hpp"
 
 using namespace mf;
 
@@ -58,6 +59,10 @@ struct mf_grid_s {
     double cs2 = 1.0 / 3.0;
     EosTable table{};               // device view of the tabulated EoS
     void* table_dev = nullptr;      // its records (library-owned)
+    float* seed_params = nullptr;   // seed network parameters (device, MF_MLP_PARAMS)
+    float* seed_grid = nullptr;     // its predictions on the (ln E, |M|/E) grid
+    SeedNorm seed_norm{};
+    bool has_seed = false;
     int seg_override[3] = {0, 0, 0};
     int block = 256;
     unsigned long long* dstats = nullptr;  // (n_events + 1) * ST_WORDS; the last slot is scratch
@@ -114,6 +119,12 @@ struct mf_grid_s {
             return hipSuccess;
         }
         return hipEventCreate(e);
+    }
+    void release(void* p)
+    {
+        if (!p) return;
+        (void)hipFree(p);
+        allocs.erase(std::remove(allocs.begin(), allocs.end(), p), allocs.end());
     }
     int alloc(void** p, size_t bytes)
     {
@@ -580,6 +591,65 @@ int batch_prepare_any(mf_grid_s* g, const double* dt)
     return batch_prepare<double>(g, EosIdeal<double>::make(g->cs2), dt);
 }
 
+// Upload the seed network and fill its prediction grid over
+// ln E in [ln 1e-4, ln 1e4] (1024 points) and |M|/E in [0, 1] (513 points).
+constexpr int kSeedG0 = 1024, kSeedG1 = 513;
+constexpr double kSeedLnLo = -9.210340371976184, kSeedLnHi = 9.210340371976184;
+
+int install_seed(mf_grid_s* g, const mf_surrogate& s)
+{
+    const int H = MF_MLP_HIDDEN;
+    std::vector<float> P(MF_MLP_PARAMS);
+    size_t o = 0;
+    for (int i = 0; i < 2 * H; i++) P[o++] = s.w1[i];
+    for (int i = 0; i < H; i++) P[o++] = s.b1[i];
+    for (int i = 0; i < H * H; i++) P[o++] = s.w2[i];
+    for (int i = 0; i < H; i++) P[o++] = s.b2[i];
+    for (int i = 0; i < H; i++) P[o++] = s.w3[i];
+    P[o++] = s.b3;
+    SeedNorm nrm;
+    for (int q = 0; q < 2; q++) {
+        nrm.in_shift[q] = s.in_shift[q];
+        nrm.in_scale[q] = s.in_scale[q];
+    }
+    nrm.out_shift = s.out_shift;
+    nrm.out_scale = s.out_scale;
+    nrm.max_newton = s.max_newton;
+    int rc = g->alloc((void**)&g->seed_params, sizeof(float) * MF_MLP_PARAMS);
+    if (!rc) rc = g->alloc((void**)&g->seed_grid, sizeof(float) * kSeedG0 * kSeedG1);
+    if (rc) return rc;
+    float* X = nullptr;
+    rc = g->alloc((void**)&X, sizeof(float) * 2 * kSeedG0 * kSeedG1);
+    if (rc) return rc;
+    std::vector<float> hx((size_t)2 * kSeedG0 * kSeedG1), hy((size_t)kSeedG0 * kSeedG1);
+    const double dl = (kSeedLnHi - kSeedLnLo) / (kSeedG0 - 1);
+    for (int i = 0; i < kSeedG0; i++)
+        for (int j = 0; j < kSeedG1; j++) {
+            const size_t k = (size_t)i * kSeedG1 + j;
+            hx[2 * k] = (float)((kSeedLnLo + i * dl - nrm.in_shift[0]) * nrm.in_scale[0]);
+            hx[2 * k + 1] = (float)(((double)j / (kSeedG1 - 1) - nrm.in_shift[1]) * nrm.in_scale[1]);
+        }
+    MF_HIP(hipMemcpy(g->seed_params, P.data(), sizeof(float) * P.size(), hipMemcpyHostToDevice));
+    MF_HIP(hipMemcpy(X, hx.data(), sizeof(float) * hx.size(), hipMemcpyHostToDevice));
+    hipError_t e = mlp_forward(g->seed_params, X, (int64_t)kSeedG0 * kSeedG1, g->seed_grid, nullptr);
+    if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("seed grid: ") + hipGetErrorString(e));
+    MF_HIP(hipDeviceSynchronize());
+    MF_HIP(hipMemcpy(hy.data(), g->seed_grid, sizeof(float) * hy.size(), hipMemcpyDeviceToHost));
+    for (float& v : hy) v = v * nrm.out_scale + nrm.out_shift;  // ln e
+    MF_HIP(hipMemcpy(g->seed_grid, hy.data(), sizeof(float) * hy.size(), hipMemcpyHostToDevice));
+    g->release(X);
+    g->seed_norm = nrm;
+    g->has_seed = true;
+    EosTable& t = g->table;
+    t.seed = g->seed_grid;
+    t.sg0 = kSeedG0;
+    t.sg1 = kSeedG1;
+    t.seed_lnE0 = (float)kSeedLnLo;
+    t.seed_inv_dlnE = (float)(1.0 / dl);
+    t.max_newton = nrm.max_newton;
+    return MF_OK;
+}
+
 int check_desc(const mf_grid_desc& d)
 {
     for (int q = 0; q < 3; q++) {
@@ -676,7 +746,8 @@ int mf_set_eos(mf_grid_t g, int32_t kind, double cs2, const double* e_tab, const
         if (i > 0 && (!(e_tab[i] > e_tab[i - 1]) || p_tab[i] < p_tab[i - 1]))
             return fail(MF_ERR_ARG, "table e must increase strictly and p must not decrease");
     }
-    if (s) return fail(MF_ERR_ARG, "the learned seed is not available in this build");
+    if (s && (s->hidden != MF_MLP_HIDDEN || !s->w1 || !s->b1 || !s->w2 || !s->b2 || !s->w3 || s->max_newton < 1))
+        return fail(MF_ERR_ARG, "the seed network must be 2-64-64-1 with all weights and max_newton >= 1");
     std::vector<double> m;
     monotone_slopes(n_tab, e_tab, p_tab, m);
     std::vector<double> rec(4 * (size_t)n_tab);
@@ -692,12 +763,14 @@ int mf_set_eos(mf_grid_t g, int32_t kind, double cs2, const double* e_tab, const
     bool log_uniform = true;
     for (int i = 0; i < n_tab && log_uniform; i++)
         log_uniform = std::fabs(std::log2(e_tab[i]) - (l0 + i * dl)) <= 1e-6 * dl;
-    if (g->table_dev) {
-        MF_HIP(hipStreamSynchronize(g->stream));
-        (void)hipFree(g->table_dev);
-        g->allocs.erase(std::remove(g->allocs.begin(), g->allocs.end(), g->table_dev), g->allocs.end());
-        g->table_dev = nullptr;
-    }
+    MF_HIP(hipStreamSynchronize(g->stream));
+    g->release(g->table_dev);
+    g->table_dev = nullptr;
+    g->release(g->seed_params);
+    g->seed_params = nullptr;
+    g->release(g->seed_grid);
+    g->seed_grid = nullptr;
+    g->has_seed = false;
     int rc = g->alloc(&g->table_dev, rec.size() * sizeof(double));
     if (rc) return rc;
     MF_HIP(hipMemcpy(g->table_dev, rec.data(), rec.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -713,7 +786,12 @@ int mf_set_eos(mf_grid_t g, int32_t kind, double cs2, const double* e_tab, const
     t.plast = p_tab[n_tab - 1];
     t.mlast = m[n_tab - 1];
     t.max_iter = 100;
+    t.seed = nullptr;
     g->eos_kind = MF_EOS_TABLE;
+    if (s) {
+        int rc2 = install_seed(g, *s);
+        if (rc2) return rc2;
+    }
     return MF_OK;
 }
 
@@ -913,15 +991,30 @@ int mf_con2prim(mf_grid_t g, const void* const U[4], void* const prim[5], int64_
     if (!g || !U || !prim) return fail(MF_ERR_ARG, "null argument");
     if (g->eos_kind < 0) return fail(MF_ERR_STATE, "no equation of state set");
     if (n < 0) return fail(MF_ERR_ARG, "n must be >= 0");
-    if (mode != MF_C2P_PLAIN) return fail(MF_ERR_ARG, "seeded con2prim needs a surrogate");
+    if (mode != MF_C2P_PLAIN && mode != MF_C2P_SEEDED && mode != MF_C2P_CONFORMAL)
+        return fail(MF_ERR_ARG, "unknown con2prim mode");
+    if (mode != MF_C2P_PLAIN && g->eos_kind != MF_EOS_TABLE)
+        return fail(MF_ERR_ARG, "seeded con2prim needs the table EoS");
+    if (mode == MF_C2P_SEEDED && !g->has_seed) return fail(MF_ERR_ARG, "seeded con2prim needs a surrogate");
     if (n == 0) return MF_OK;
     for (int c = 0; c < 4; c++)
         if (!U[c]) return fail(MF_ERR_ARG, "null state pointer");
     for (int c = 0; c < 5; c++)
         if (!prim[c]) return fail(MF_ERR_ARG, "null output pointer");
     unsigned long long* stats = g->dstats + (size_t)ST_WORDS * g->ev.size();
-    hipError_t e;
-    if (g->eos_kind == MF_EOS_TABLE) {
+    hipError_t e = launch_fill_u64(g->stream, stats, ST_WORDS, 0ULL);
+    if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("stats reset: ") + hipGetErrorString(e));
+    if (mode != MF_C2P_PLAIN) {
+        C2PArgs<double> a;
+        for (int c = 0; c < 4; c++) a.U[c] = (const double*)U[c];
+        for (int c = 0; c < 5; c++) a.prim[c] = (double*)prim[c];
+        a.iters = iters_dev; a.n = n; a.stats = stats;
+        EosTable t = g->table;
+        t.seed = nullptr;
+        SeedNorm nrm = g->seed_norm;
+        if (!g->has_seed) nrm.max_newton = 3;
+        e = con2prim_seeded(n, g->stream, a, t, g->seed_params, nrm, mode == MF_C2P_SEEDED ? 1 : 2);
+    } else if (g->eos_kind == MF_EOS_TABLE) {
         C2PArgs<double> a;
         for (int c = 0; c < 4; c++) a.U[c] = (const double*)U[c];
         for (int c = 0; c < 5; c++) a.prim[c] = (double*)prim[c];
@@ -943,6 +1036,49 @@ int mf_con2prim(mf_grid_t g, const void* const U[4], void* const prim[5], int64_
         e = launch_con2prim<double, EosIdeal<double>>(n, g->stream, a, eos);
     }
     if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("con2prim launch: ") + hipGetErrorString(e));
+    return MF_OK;
+}
+
+int mf_con2prim_stats(mf_grid_t g, int64_t out[4])
+{
+    if (!g || !out) return fail(MF_ERR_ARG, "null argument");
+    unsigned long long h[ST_WORDS];
+    MF_HIP(hipMemcpyAsync(h, g->dstats + (size_t)ST_WORDS * g->ev.size(), sizeof(h), hipMemcpyDeviceToHost,
+                          g->stream));
+    MF_HIP(hipStreamSynchronize(g->stream));
+    out[0] = (int64_t)h[ST_FLOOR];
+    out[1] = (int64_t)h[ST_BAD];
+    out[2] = (int64_t)h[ST_ITERS];
+    out[3] = (int64_t)h[ST_FALLBACK];
+    return MF_OK;
+}
+
+int64_t mf_mlp_workspace(int64_t n) { return n > 0 ? mlp_grad_partials(n) * (MF_MLP_PARAMS + 1) : 0; }
+
+int mf_mlp_forward(const float* params, const float* X, int64_t n, float* y, void* stream)
+{
+    if (!params || !X || !y || n < 0) return fail(MF_ERR_ARG, "bad argument");
+    hipError_t e = mlp_forward(params, X, n, y, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("mlp forward: ") + hipGetErrorString(e));
+    return MF_OK;
+}
+
+int mf_mlp_grad(const float* params, const float* X, const float* t, int64_t n, float* grad, float* loss, float* work,
+                int64_t work_floats, void* stream)
+{
+    if (!params || !X || !t || !grad || !work || n < 1) return fail(MF_ERR_ARG, "bad argument");
+    if (work_floats < mf_mlp_workspace(n)) return fail(MF_ERR_ARG, "workspace too small (see mf_mlp_workspace)");
+    hipError_t e = mlp_grad(params, X, t, n, work, grad, loss, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("mlp grad: ") + hipGetErrorString(e));
+    return MF_OK;
+}
+
+int mf_mlp_adam(float* params, const float* grad, float* m, float* v, int32_t step, float lr, float beta1, float beta2,
+                float eps, void* stream)
+{
+    if (!params || !grad || !m || !v || step < 1 || !(lr > 0.0f)) return fail(MF_ERR_ARG, "bad argument");
+    hipError_t e = mlp_adam(params, grad, m, v, step, lr, beta1, beta2, eps, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("mlp adam: ") + hipGetErrorString(e));
     return MF_OK;
 }
 

@@ -19,12 +19,13 @@ MF_BC_OUTFLOW, MF_BC_PERIODIC = 0, 1
 MF_F64, MF_F32 = 0, 1
 MF_LIM_NONE, MF_LIM_MINMOD, MF_LIM_SUPERBEE, MF_LIM_MC, MF_LIM_VANLEER, MF_LIM_VANALBADA = range(6)
 MF_EOS_IDEAL, MF_EOS_TABLE = 0, 1
-MF_C2P_PLAIN, MF_C2P_SEEDED = 0, 1
+MF_C2P_PLAIN, MF_C2P_SEEDED, MF_C2P_CONFORMAL = 0, 1, 2
+MF_MLP_HIDDEN, MF_MLP_PARAMS = 64, 4417
 MF_FLAG_STRICT = 1
 
 EXPORTS = ["mf_grid_init", "mf_set_eos", "mf_set_source_jet", "mf_set_time", "mf_step", "mf_batch_step",
-           "mf_con2prim", "mf_totals", "mf_set_tuning", "mf_set_profiling", "mf_get_profile", "mf_grid_free",
-           "mf_last_error"]
+           "mf_con2prim", "mf_con2prim_stats", "mf_totals", "mf_set_tuning", "mf_set_profiling", "mf_get_profile",
+           "mf_grid_free", "mf_last_error", "mf_mlp_workspace", "mf_mlp_forward", "mf_mlp_grad", "mf_mlp_adam"]
 
 
 class GridDesc(C.Structure):
@@ -82,9 +83,15 @@ def lib():
         L.mf_set_profiling.argtypes = [vp, C.c_int32]
         L.mf_get_profile.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.mf_grid_free.argtypes = [vp]
+        L.mf_con2prim_stats.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.mf_mlp_workspace.argtypes = [C.c_int64]
+        L.mf_mlp_forward.argtypes = [vp, vp, C.c_int64, vp, vp]
+        L.mf_mlp_grad.argtypes = [vp, vp, vp, C.c_int64, vp, vp, vp, C.c_int64, vp]
+        L.mf_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, vp]
         for name in EXPORTS:
-            if name != "mf_last_error":
+            if name not in ("mf_last_error", "mf_mlp_workspace"):
                 getattr(L, name).restype = C.c_int
+        L.mf_mlp_workspace.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -157,13 +164,15 @@ class Grid:
     def set_eos_ideal(self, cs2=1.0 / 3.0):
         _check(lib().mf_set_eos(self.h, MF_EOS_IDEAL, float(cs2), None, None, 0, None))
 
-    def set_eos_table(self, e, p, surrogate: Surrogate | None = None):
+    def set_eos_table(self, e, p, surrogate=None):
+        """surrogate: None or a SeedNetwork (keeps its arrays alive)."""
         import numpy as np
         e = np.ascontiguousarray(e, dtype=np.float64)
         p = np.ascontiguousarray(p, dtype=np.float64)
         D = C.POINTER(C.c_double)
+        s = surrogate.struct() if surrogate is not None else None
         _check(lib().mf_set_eos(self.h, MF_EOS_TABLE, 0.0, e.ctypes.data_as(D), p.ctypes.data_as(D), len(e),
-                                C.byref(surrogate) if surrogate is not None else None))
+                                C.byref(s) if s is not None else None))
 
     def set_jet(self, event, x0, v, dedx, sigma):
         x = (C.c_double * 3)(*[float(q) for q in x0])
@@ -212,6 +221,12 @@ class Grid:
         _check(lib().mf_get_profile(self.h, ms, n))
         return list(ms), list(n)
 
+    def con2prim_stats(self):
+        """Counters of the last con2prim call: (clamped, bad, iterations, seeded restarts)."""
+        out = (C.c_int64 * 4)()
+        _check(lib().mf_con2prim_stats(self.h, out))
+        return list(out)
+
     def totals(self, event=0):
         out = (C.c_double * 4)()
         _check(lib().mf_totals(self.h, int(event), out))
@@ -227,3 +242,54 @@ class Grid:
             self.free()
         except Exception:
             pass
+
+
+class SeedNetwork:
+    """Host copy of the seed network's FP32 weights and normalisation (for mf_set_eos)."""
+
+    def __init__(self, params, in_shift, in_scale, out_shift, out_scale, max_newton=3):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != MF_MLP_PARAMS:
+            raise ValueError(f"expected {MF_MLP_PARAMS} parameters")
+        H = MF_MLP_HIDDEN
+        o = np.cumsum([0, 2 * H, H, H * H, H, H])
+        self.params = p
+        self.w1, self.b1, self.w2, self.b2, self.w3 = (np.ascontiguousarray(p[o[i]:o[i + 1]]) for i in range(5))
+        self.b3 = float(p[-1])
+        self.in_shift, self.in_scale = [float(v) for v in in_shift], [float(v) for v in in_scale]
+        self.out_shift, self.out_scale = float(out_shift), float(out_scale)
+        self.max_newton = int(max_newton)
+
+    def struct(self) -> Surrogate:
+        F = C.POINTER(C.c_float)
+        s = Surrogate()
+        s.hidden = MF_MLP_HIDDEN
+        s.w1, s.b1, s.w2, s.b2, s.w3 = (a.ctypes.data_as(F) for a in (self.w1, self.b1, self.w2, self.b2, self.w3))
+        s.b3 = self.b3
+        s.in_shift[:] = self.in_shift
+        s.in_scale[:] = self.in_scale
+        s.out_shift, s.out_scale, s.max_newton = self.out_shift, self.out_scale, self.max_newton
+        return s
+
+
+def mlp_forward(params, X, y, stream=None):
+    """y = MLP(X) on the device (torch tensors: params (4417,), X (n, 2), y (n,), float32)."""
+    st = stream.cuda_stream if stream is not None else None
+    _check(lib().mf_mlp_forward(_ptr(params), _ptr(X), X.shape[0], _ptr(y), st))
+
+
+def mlp_workspace(n) -> int:
+    return int(lib().mf_mlp_workspace(int(n)))
+
+
+def mlp_grad(params, X, t, grad, loss, work, stream=None):
+    st = stream.cuda_stream if stream is not None else None
+    _check(lib().mf_mlp_grad(_ptr(params), _ptr(X), _ptr(t), X.shape[0], _ptr(grad),
+                             _ptr(loss) if loss is not None else None, _ptr(work), work.numel(), st))
+
+
+def mlp_adam(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    st = stream.cuda_stream if stream is not None else None
+    _check(lib().mf_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr), float(beta1),
+                             float(beta2), float(eps), st))

@@ -1,0 +1,167 @@
+"""The learned con2prim seed on the GPU.
+
+* Forward and gradient of the BF16 matrix-core kernels against the CPU
+  reference with the same rounding points (relative 1e-3).
+* Training on solver-generated crossover-EoS states lowers the loss.
+* Seeded con2prim (network on the matrix cores, and the prediction grid used
+  by the sweeps) equals the plain bracketed Newton to 1e-12 per state, and a
+  seeded run equals a plain run to 1e-10.
+* The gain: Newton iterations and time, seeded vs plain vs the conformal guess.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as ref
+from paper_1510_06340_amd import inputs as I
+from paper_1510_06340_amd import mf, surrogate
+from helpers import gpu_run, max_rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TABLE = I.crossover_table()
+
+
+def params_dict(flat):
+    H = 64
+    o = np.cumsum([0, 2 * H, H, H * H, H, H])
+    f = np.asarray(flat, dtype=np.float64)
+    return {"W1": f[o[0]:o[1]].reshape(H, 2), "b1": f[o[1]:o[2]], "W2": f[o[2]:o[3]].reshape(H, H),
+            "b2": f[o[3]:o[4]], "w3": f[o[4]:o[5]], "b3": float(f[-1])}
+
+
+def flat_grads(g):
+    return np.concatenate([g["W1"].ravel(), g["b1"], g["W2"].ravel(), g["b2"], g["w3"], [g["b3"]]])
+
+
+def random_net(seed):
+    rng = np.random.default_rng(seed)
+    p = surrogate.init_params(seed).astype(np.float64)
+    p[128:192] = rng.normal(size=64) * 0.2           # b1
+    p[192 + 4096:192 + 4096 + 64] = rng.normal(size=64) * 0.2  # b2
+    p[-1] = 0.1
+    return p.astype(np.float32)
+
+
+@pytest.mark.parametrize("n", [64, 1000, 4096])
+def test_mlp_forward_matches_reference(n):
+    import torch
+    rng = np.random.default_rng(n)
+    p = random_net(1)
+    X = rng.normal(size=(n, 2)).astype(np.float32)
+    y = torch.empty(n, device="cuda")
+    mf.mlp_forward(torch.from_numpy(p).cuda(), torch.from_numpy(X).cuda(), y)
+    yr, _ = ref.forward(params_dict(p), X.astype(np.float64), rnd=True)
+    np.testing.assert_allclose(y.cpu().numpy(), yr, rtol=1e-3, atol=1e-3 * np.abs(yr).max())
+
+
+@pytest.mark.parametrize("n", [64, 777, 4096])
+def test_mlp_gradients_match_reference(n):
+    import torch
+    rng = np.random.default_rng(10 + n)
+    p = random_net(2)
+    X = rng.normal(size=(n, 2)).astype(np.float32)
+    t = rng.normal(size=n).astype(np.float32)
+    P = torch.from_numpy(p).cuda()
+    grad = torch.zeros_like(P)
+    loss = torch.zeros(1, device="cuda")
+    work = torch.empty(mf.mlp_workspace(n), device="cuda")
+    mf.mlp_grad(P, torch.from_numpy(X).cuda(), torch.from_numpy(t).cuda(), grad, loss, work)
+    lr_, gr, _ = ref.loss_and_grads(params_dict(p), X.astype(np.float64), t.astype(np.float64), rnd=True)
+    gg = grad.cpu().numpy().astype(np.float64)
+    gref = flat_grads(gr)
+    assert float(loss.cpu()[0]) == pytest.approx(lr_, rel=1e-3)
+    H = 64
+    o = np.cumsum([0, 2 * H, H, H * H, H, H, 1])
+    for name, a, b in zip(["W1", "b1", "W2", "b2", "w3", "b3"], o[:-1], o[1:]):
+        err = np.linalg.norm(gg[a:b] - gref[a:b]) / max(np.linalg.norm(gref[a:b]), 1e-30)
+        assert err <= 1e-3, (name, err)
+
+
+def test_adam_step_matches_formula():
+    import torch
+    rng = np.random.default_rng(3)
+    p = rng.normal(size=mf.MF_MLP_PARAMS).astype(np.float32)
+    g = rng.normal(size=mf.MF_MLP_PARAMS).astype(np.float32)
+    P, G = torch.from_numpy(p.copy()).cuda(), torch.from_numpy(g).cuda()
+    m, v = torch.zeros_like(P), torch.zeros_like(P)
+    for step in (1, 2):
+        mf.mlp_adam(P, G, m, v, step, 1e-2)
+    # two Adam steps with the same gradient, bias-corrected: each moves by lr * g / (|g| + eps)
+    expect = p - 2 * 1e-2 * g / (np.abs(g) + 1e-8)
+    np.testing.assert_allclose(P.cpu().numpy(), expect, rtol=1e-4, atol=1e-6)
+
+
+@pytest.fixture(scope="module")
+def trained():
+    E, M = surrogate.collect_states(n_samples=1 << 20, n=64, steps=30, snap_every=5)
+    e = surrogate.label_states(E, M)
+    net = surrogate.train(E, M, e, epochs=20, batch=4096)
+    return dict(E=E, M=M, e=e, net=net)
+
+
+def test_training_lowers_the_loss(trained):
+    h = trained["net"].history
+    print("\nepoch, train loss, validation loss:", [(a, round(b, 6), round(c, 6)) for a, b, c in h[::4] + h[-1:]])
+    assert h[-1][1] < 0.2 * h[0][1] and h[-1][2] < 0.2 * h[0][2]
+    err = surrogate.relative_error(trained["net"], trained["E"], trained["M"], trained["e"])
+    print(f"relative error of the seed: median {float(err.median()):.2e}, 99% {float(err.quantile(0.99)):.2e}")
+    assert float(err.median()) < 0.05
+
+
+def run_c2p(E, M, mode, net=None):
+    import torch
+    n = E.numel()
+    U = [E.contiguous(), M.contiguous(), torch.zeros_like(E), torch.zeros_like(E)]
+    prim = [torch.empty_like(E) for _ in range(5)]
+    it = torch.zeros(n, dtype=torch.int32, device="cuda")
+    g = mf.Grid([mf.make_desc((n, 1, 1), (1, 1, 1), (0, 0, 0), (0, 0, 0))], [U])
+    g.set_eos_table(*TABLE, surrogate=net)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g.con2prim(U, prim, it, mode)  # warm-up
+    start.record()
+    g.con2prim(U, prim, it, mode)
+    stop.record()
+    torch.cuda.synchronize()
+    stats = g.con2prim_stats()
+    g.free()
+    return prim[0], it, stats, start.elapsed_time(stop)
+
+
+def test_seeded_con2prim_equals_plain(trained):
+    """P13: every seeded solution equals the plain one to 1e-12 relative; fewer iterations."""
+    net = trained["net"].network(max_newton=3)
+    E, M = trained["E"], trained["M"]
+    ep, itp, _, tp = run_c2p(E, M, mf.MF_C2P_PLAIN, net)
+    es, its, sts, ts = run_c2p(E, M, mf.MF_C2P_SEEDED, net)
+    ec, itc, stc, tc = run_c2p(E, M, mf.MF_C2P_CONFORMAL, net)
+    for x in (es, ec):
+        rel = ((x - ep).abs() / ep).max().item()
+        assert rel <= 1e-12, rel
+    mp, ms, mc = float(itp.float().mean()), float(its.float().mean()), float(itc.float().mean())
+    print(f"\nmean Newton iterations: plain {mp:.3f}, learned seed {ms:.3f} (restarts {sts[3]}), "
+          f"conformal {mc:.3f} (restarts {stc[3]}); time ms plain {tp:.3f} seeded {ts:.3f} conformal {tc:.3f}")
+    assert ms < mp
+    assert sts[3] < 0.05 * E.numel()
+
+
+def test_seeded_run_equals_plain_run(trained):
+    """A crossover-EoS run with the learned seed (prediction grid in the sweeps) equals the plain run to 1e-10."""
+    net = trained["net"].network(max_newton=3)
+    w = I.crossover_workloads(n_events=1, n=40, steps=5)[0]
+    U = I.initial_state(w)
+    Up, stp = gpu_run(w, U, eos_table=TABLE)
+    import torch
+    dev = to_dev(U)
+    g = mf.Grid([mf.desc_from_workload(w)], [dev])
+    g.set_eos_table(*TABLE, surrogate=net)
+    sts = g.step(w.dt, w.steps)[0]
+    torch.cuda.synchronize()
+    Us = np.stack([t.cpu().numpy().reshape(U.shape[1:]) for t in dev])
+    g.free()
+    assert max_rel_err(Us, Up) <= 1e-10
+    Uo, _ = oracle.step(oracle.Problem.from_workload(w, table=TABLE), U, w.dt, w.steps)
+    assert max_rel_err(Us, Uo) <= 1e-10
+    print(f"\nstep iterations: plain {stp['newton_iters']}, seeded {sts['newton_iters']} "
+          f"(restarts {sts['n_fallback']})")
+    assert sts["newton_iters"] < stp["newton_iters"]
