@@ -118,7 +118,7 @@ def run_single(args, w, U, table=None, jet_x0=None):
     return ms_total, kms, klaunch, st
 
 
-def run_events(args, ws, Us, batched, table=None):
+def run_events(args, ws, Us, batched, table=None, seed_net=None):
     """Many events: one batched handle (mf_batch_step) or one mf_step call per event in turn."""
     import torch
     from paper_1510_06340_amd import mf
@@ -129,7 +129,7 @@ def run_events(args, ws, Us, batched, table=None):
         if table is None:
             g.set_eos_ideal()
         else:
-            g.set_eos_table(*table)
+            g.set_eos_table(*table, surrogate=seed_net)
     dts = [w.dt for w in ws]
     per = []
     if not batched:
@@ -289,6 +289,23 @@ def bench_events(args, I):
         args.steps = ws[0].steps
     Us = [I.initial_state(w) for w in ws]
     cells = sum(w.cells for w in ws)
+    seeded = None
+    if args.workload == "crossover":
+        import time
+        from paper_1510_06340_amd import surrogate
+        t0 = time.perf_counter()
+        E, M = surrogate.collect_states(n_samples=1 << 22, seed=42, n=128)
+        e = surrogate.label_states(E, M, table)
+        net = surrogate.train(E, M, e, epochs=30)
+        err = surrogate.relative_error(net, E, M, e)
+        train_s = time.perf_counter() - t0
+        ms_s, st_s = run_events(args, ws, Us, batched=True, table=table, seed_net=net.network(max_newton=3))
+        seeded = {"value": cells * args.steps / (ms_s / 1e3), "ms_per_step": ms_s / args.steps,
+                  "newton_iters": sum(s["newton_iters"] for s in st_s),
+                  "restarts": sum(s["n_fallback"] for s in st_s),
+                  "train": {"states": int(E.numel()), "epochs": 30, "seconds": train_s,
+                            "val_loss": net.history[-1][2], "seed_rel_err_median": float(err.median()),
+                            "seed_rel_err_p99": float(err.quantile(0.99))}}
     ms_b, st_b = run_events(args, ws, Us, batched=True, table=table)
     ms_p, st_p = run_events(args, ws, Us, batched=False, table=table)
     value = cells * args.steps / (ms_b / 1e3)
@@ -310,6 +327,7 @@ def bench_events(args, I):
         "data": "synthetic",
         "config": {"workload": desc, "cells": cells, "form": "batched (persistent tile queue, graph replay)"},
         "plain_per_event": {"value": plain, "ms_per_step": ms_p / args.steps, "speedup_batched": value / plain},
+        "batched_seeded": seeded,
         "roofline": {"kernel": "k_batch_sweep (all sweeps of the step)", "bound": "alu", "achieved": achieved,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": None, "note": "whole-step average (graph replay, no per-launch events)"},
