@@ -110,6 +110,8 @@ typedef struct {
     float in_shift[2], in_scale[2];
     float out_shift, out_scale;
     int32_t max_newton;  /* seeded Newton iterations before the plain fallback (e.g. 3) */
+    int32_t output;      /* 0: the network predicts ln e (as configured);
+                            1: it predicts the bracket fraction (E - e) E / |M|^2, so e = E - y |M|^2 / E */
 } mf_surrogate;
 
 /* Create a handle for n_events independent grids (Sec. 2.1 problem statement,

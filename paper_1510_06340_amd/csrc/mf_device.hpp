@@ -210,6 +210,7 @@ struct EosTable {
     int32_t sg0, sg1;
     float seed_lnE0, seed_inv_dlnE;  // grid origin and inverse spacing in ln E
     int32_t max_newton;              // seeded Newton iterations before the plain restart
+    int32_t seed_output;             // 0: grid holds ln e; 1: the bracket fraction (E - e) E / |M|^2
 
     __device__ __forceinline__ void eval(double e, double& p, double& dp) const
     {
@@ -321,7 +322,7 @@ struct EosTable {
         return solve(E, M2, 0.5 * (lo + hi), cnt);
     }
 
-    // Bilinear read of the seed grid at (ln E, m); returns e0 = exp(ln e).
+    // Bilinear read of the seed grid at (ln E, m); returns the guess e0.
     __device__ __forceinline__ double seed_guess(double E, double M2) const
     {
         const float lnE = __builtin_amdgcn_logf((float)E) * 0.69314718f;
@@ -335,6 +336,7 @@ struct EosTable {
         const float* r0 = seed + (int64_t)i * sg1 + j;
         const float* r1 = r0 + sg1;
         const float y = (1.0f - fu) * ((1.0f - fv) * r0[0] + fv * r0[1]) + fu * ((1.0f - fv) * r1[0] + fv * r1[1]);
+        if (seed_output == 1) return E - (double)y * M2 * Math<double>::rcp(E);
         return (double)__expf(y);
     }
 

@@ -343,7 +343,8 @@ __global__ __launch_bounds__(256) void k_con2prim_seeded(C2PArgs<double> a, EosT
     if (M2 != 0.0) {
         double e0;
         if (mode == 1) {
-            e0 = exp((double)(y * nrm.out_scale + nrm.out_shift));
+            const double pred = (double)(y * nrm.out_scale + nrm.out_shift);
+            e0 = nrm.output == 1 ? E - pred * M2 / E : exp(pred);
         } else {
             const double c = 1.0 / 3.0, q = 1.0 + c;
             e0 = E - 2.0 * M2 / (q * E + sqrt(q * q * E * E - 4.0 * c * M2));

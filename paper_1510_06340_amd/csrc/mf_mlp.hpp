@@ -17,8 +17,9 @@ constexpr int kMlpParams = 2 * kMlpHidden + kMlpHidden + kMlpHidden * kMlpHidden
 // Input/output normalisation of the seed network.
 struct SeedNorm {
     float in_shift[2], in_scale[2];  // x = ((ln E, |M|/E) - shift) * scale
-    float out_shift, out_scale;      // ln e = y * scale + shift
+    float out_shift, out_scale;      // prediction = y * scale + shift
     int max_newton;
+    int output;                      // 0: prediction = ln e; 1: = (E - e) E / |M|^2
 };
 
 // Seeded con2prim over n states (mode 1: MLP on the matrix cores, mode 2:

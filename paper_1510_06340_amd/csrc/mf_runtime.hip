@@ -615,6 +615,7 @@ int install_seed(mf_grid_s* g, const mf_surrogate& s)
     nrm.out_shift = s.out_shift;
     nrm.out_scale = s.out_scale;
     nrm.max_newton = s.max_newton;
+    nrm.output = s.output;
     int rc = g->alloc((void**)&g->seed_params, sizeof(float) * MF_MLP_PARAMS);
     if (!rc) rc = g->alloc((void**)&g->seed_grid, sizeof(float) * kSeedG0 * kSeedG1);
     if (rc) return rc;
@@ -635,7 +636,7 @@ int install_seed(mf_grid_s* g, const mf_surrogate& s)
     if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("seed grid: ") + hipGetErrorString(e));
     MF_HIP(hipDeviceSynchronize());
     MF_HIP(hipMemcpy(hy.data(), g->seed_grid, sizeof(float) * hy.size(), hipMemcpyDeviceToHost));
-    for (float& v : hy) v = v * nrm.out_scale + nrm.out_shift;  // ln e
+    for (float& v : hy) v = v * nrm.out_scale + nrm.out_shift;  // ln e or the bracket fraction
     MF_HIP(hipMemcpy(g->seed_grid, hy.data(), sizeof(float) * hy.size(), hipMemcpyHostToDevice));
     g->release(X);
     g->seed_norm = nrm;
@@ -647,6 +648,7 @@ int install_seed(mf_grid_s* g, const mf_surrogate& s)
     t.seed_lnE0 = (float)kSeedLnLo;
     t.seed_inv_dlnE = (float)(1.0 / dl);
     t.max_newton = nrm.max_newton;
+    t.seed_output = nrm.output;
     return MF_OK;
 }
 
@@ -746,8 +748,9 @@ int mf_set_eos(mf_grid_t g, int32_t kind, double cs2, const double* e_tab, const
         if (i > 0 && (!(e_tab[i] > e_tab[i - 1]) || p_tab[i] < p_tab[i - 1]))
             return fail(MF_ERR_ARG, "table e must increase strictly and p must not decrease");
     }
-    if (s && (s->hidden != MF_MLP_HIDDEN || !s->w1 || !s->b1 || !s->w2 || !s->b2 || !s->w3 || s->max_newton < 1))
-        return fail(MF_ERR_ARG, "the seed network must be 2-64-64-1 with all weights and max_newton >= 1");
+    if (s && (s->hidden != MF_MLP_HIDDEN || !s->w1 || !s->b1 || !s->w2 || !s->b2 || !s->w3 || s->max_newton < 1 ||
+              (s->output != 0 && s->output != 1)))
+        return fail(MF_ERR_ARG, "the seed network must be 2-64-64-1 with all weights, max_newton >= 1, output 0 or 1");
     std::vector<double> m;
     monotone_slopes(n_tab, e_tab, p_tab, m);
     std::vector<double> rec(4 * (size_t)n_tab);
@@ -1019,7 +1022,9 @@ int mf_con2prim(mf_grid_t g, const void* const U[4], void* const prim[5], int64_
         for (int c = 0; c < 4; c++) a.U[c] = (const double*)U[c];
         for (int c = 0; c < 5; c++) a.prim[c] = (double*)prim[c];
         a.iters = iters_dev; a.n = n; a.stats = stats;
-        e = launch_con2prim<double, EosTable>(n, g->stream, a, g->table);
+        EosTable t = g->table;
+        t.seed = nullptr;  // plain: bracket midpoint start, whether or not a seed is installed
+        e = launch_con2prim<double, EosTable>(n, g->stream, a, t);
     } else if (g->ev[0].d.dtype == MF_F32) {
         C2PArgs<float> a;
         for (int c = 0; c < 4; c++) a.U[c] = (const float*)U[c];

@@ -49,7 +49,8 @@ class Surrogate(C.Structure):
     _fields_ = [("hidden", C.c_int32), ("w1", C.POINTER(C.c_float)), ("b1", C.POINTER(C.c_float)),
                 ("w2", C.POINTER(C.c_float)), ("b2", C.POINTER(C.c_float)), ("w3", C.POINTER(C.c_float)),
                 ("b3", C.c_float), ("in_shift", C.c_float * 2), ("in_scale", C.c_float * 2),
-                ("out_shift", C.c_float), ("out_scale", C.c_float), ("max_newton", C.c_int32)]
+                ("out_shift", C.c_float), ("out_scale", C.c_float), ("max_newton", C.c_int32),
+                ("output", C.c_int32)]
 
 
 class MFError(RuntimeError):
@@ -247,7 +248,7 @@ class Grid:
 class SeedNetwork:
     """Host copy of the seed network's FP32 weights and normalisation (for mf_set_eos)."""
 
-    def __init__(self, params, in_shift, in_scale, out_shift, out_scale, max_newton=3):
+    def __init__(self, params, in_shift, in_scale, out_shift, out_scale, max_newton=3, output=0):
         import numpy as np
         p = np.ascontiguousarray(params, dtype=np.float32)
         if p.size != MF_MLP_PARAMS:
@@ -260,6 +261,7 @@ class SeedNetwork:
         self.in_shift, self.in_scale = [float(v) for v in in_shift], [float(v) for v in in_scale]
         self.out_shift, self.out_scale = float(out_shift), float(out_scale)
         self.max_newton = int(max_newton)
+        self.output = int(output)
 
     def struct(self) -> Surrogate:
         F = C.POINTER(C.c_float)
@@ -270,6 +272,7 @@ class SeedNetwork:
         s.in_shift[:] = self.in_shift
         s.in_scale[:] = self.in_scale
         s.out_shift, s.out_scale, s.max_newton = self.out_shift, self.out_scale, self.max_newton
+        s.output = self.output
         return s
 
 

@@ -7,7 +7,8 @@
    reservoir-sampled (random keys from a seeded generator, smallest keys kept).
 2. Labels: the plain bracketed-Newton con2prim (mf_con2prim, MF_C2P_PLAIN).
 3. Network: 2 -> 64 -> 64 -> 1 tanh on x = ((ln E, |M|/E) - mean) / std,
-   predicting the standardised ln e; trained with Adam on the mean squared
+   predicting the standardised ln e (as configured) or, optionally, the
+   root's position in the bracket [E(1 - m^2), E]; trained with Adam on the mean squared
    error by the BF16 matrix-core kernels (mf_mlp_grad / mf_mlp_adam), 90/10
    train/validation split.
 
@@ -97,22 +98,36 @@ def label_states(E, Mabs, table=None):
 
 
 class Trained:
-    def __init__(self, params, norm, history):
+    def __init__(self, params, norm, history, output):
         self.params = params        # numpy float32 (MF_MLP_PARAMS,)
         self.norm = norm            # dict in_shift, in_scale, out_shift, out_scale
         self.history = history      # list of (epoch, train_loss, val_loss)
+        self.output = output        # 0: ln e, 1: bracket fraction (E - e) E / |M|^2
 
     def network(self, max_newton=3) -> mf.SeedNetwork:
         n = self.norm
-        return mf.SeedNetwork(self.params, n["in_shift"], n["in_scale"], n["out_shift"], n["out_scale"], max_newton)
+        return mf.SeedNetwork(self.params, n["in_shift"], n["in_scale"], n["out_shift"], n["out_scale"], max_newton,
+                              self.output)
+
+    def predict_e(self, E, Mabs, y):
+        """Guess e from the network output y (standardised)."""
+        n = self.norm
+        pred = y.double() * n["out_scale"] + n["out_shift"]
+        if self.output == 1:
+            return E - pred * Mabs * Mabs / E
+        import torch
+        return torch.exp(pred)
 
 
-def train(E, Mabs, e, epochs=30, batch=4096, lr=2e-3, lr_min=2e-5, seed=0, val_frac=0.1):
-    """Fit ln e from (ln E, |M|/E) with the matrix-core kernels; returns a Trained network."""
+def train(E, Mabs, e, epochs=30, batch=4096, lr=2e-3, lr_min=2e-5, seed=0, val_frac=0.1, output=0):
+    """Fit the seed from (ln E, |M|/E) with the matrix-core kernels; returns a Trained network.
+
+    output 0: the target is ln e (as configured); output 1: the target is the
+    position of the root in the bracket [E(1 - m^2), E], (E - e) E / |M|^2."""
     import torch
     x0 = torch.log(E)
     x1 = Mabs / E
-    y = torch.log(e)
+    y = torch.log(e) if output == 0 else (E - e) * E / (Mabs * Mabs)
     mu = [float(x0.mean()), float(x1.mean())]
     sd = [float(x0.std()), float(x1.std())]
     ym, ys = float(y.mean()), float(y.std())
@@ -152,7 +167,7 @@ def train(E, Mabs, e, epochs=30, batch=4096, lr=2e-3, lr_min=2e-5, seed=0, val_f
         vl = float(((yv - Tv) ** 2).mean())
         history.append((ep, float(tr) / max(nb, 1), vl))
     norm = dict(in_shift=mu, in_scale=[1.0 / sd[0], 1.0 / sd[1]], out_shift=ym, out_scale=ys)
-    return Trained(P.cpu().numpy(), norm, history)
+    return Trained(P.cpu().numpy(), norm, history, output)
 
 
 def relative_error(trained: Trained, E, Mabs, e):
@@ -164,5 +179,4 @@ def relative_error(trained: Trained, E, Mabs, e):
     y = torch.empty(X.shape[0], device="cuda")
     P = torch.from_numpy(trained.params).cuda()
     mf.mlp_forward(P, X, y)
-    pred = torch.exp(y.double() * n["out_scale"] + n["out_shift"])
-    return (pred - e).abs() / e
+    return (trained.predict_e(E, Mabs, y) - e).abs() / e
