@@ -295,17 +295,17 @@ def bench_events(args, I):
         from paper_1510_06340_amd import surrogate
         t0 = time.perf_counter()
         E, M = surrogate.collect_states(n_samples=1 << 22, seed=42, n=128)
-        e = surrogate.label_states(E, M, table)
+        e, pr = surrogate.label_states(E, M, table)
         seeded = {"collect_label_seconds": time.perf_counter() - t0}
         for name, output in (("ln_e", 0), ("bracket_fraction", 1)):
             t0 = time.perf_counter()
-            net = surrogate.train(E, M, e, epochs=30, output=output)
+            net = surrogate.train(E, M, e, pr, epochs=30, output=output)
             err = surrogate.relative_error(net, E, M, e)
             train_s = time.perf_counter() - t0
-            ms_s, st_s = run_events(args, ws, Us, batched=True, table=table, seed_net=net.network(max_newton=3))
+            ms_s, st_s = run_events(args, ws, Us, batched=True, table=table, seed_net=net.network())
             seeded[name] = {"value": cells * args.steps / (ms_s / 1e3), "ms_per_step": ms_s / args.steps,
                             "newton_iters": sum(s["newton_iters"] for s in st_s),
-                            "restarts": sum(s["n_fallback"] for s in st_s),
+                            "guesses_outside_bracket": sum(s["n_fallback"] for s in st_s),
                             "train": {"states": int(E.numel()), "epochs": 30, "seconds": train_s,
                                       "val_loss": net.history[-1][2], "seed_rel_err_median": float(err.median()),
                                       "seed_rel_err_p99": float(err.quantile(0.99))}}

@@ -90,15 +90,20 @@ typedef struct {
     int64_t n_floor;      /* con2prim calls whose |M| was clamped to (1 - 1e-12) E */
     int64_t n_bad;        /* con2prim calls with E <= 0 or non-finite input */
     int64_t newton_iters; /* Newton / bisection iterations of the table EoS */
-    int64_t n_fallback;   /* seeded con2prim calls that fell back to the plain solve */
+    int64_t n_fallback;   /* seeded con2prim solves whose guess lay outside the bracket (started at its midpoint) */
 } mf_stats;
 
 /* Optional learned con2prim seed for MF_EOS_TABLE: a 2 -> H -> H -> 1 tanh
  * MLP (H = 64) on x = ((ln E - in_shift[0]) * in_scale[0], (|M|/E - in_shift[1]) * in_scale[1])
- * predicting ln e = out_scale * y + out_shift.  Weights row-major FP32 host
- * arrays, copied by mf_set_eos and rounded to bfloat16 on the device.  The
- * sweeps read the network's predictions from a (ln E, |M|/E) grid the network
- * fills once per mf_set_eos; mf_con2prim(MF_C2P_SEEDED) evaluates it per state. */
+ * predicting z = out_scale * y + out_shift (ln e, or the bracket fraction, by
+ * `output`).  Weights row-major FP32 host arrays, copied by mf_set_eos and
+ * rounded to bfloat16 on the device.  The sweeps read the network's
+ * predictions from a (ln E, |M|/E) grid the network fills once per
+ * mf_set_eos; mf_con2prim(MF_C2P_SEEDED) evaluates it per state.  The guess
+ * starts the same safeguarded Newton solve as the plain one (Sec. 2.6 inverse)
+ * if it lies strictly inside the bracket [E - |M|^2/E, E], else the solve
+ * starts at the bracket midpoint; results equal the plain solve's to the
+ * solver's tolerance either way. */
 typedef struct {
     int32_t hidden;      /* H (multiple of 16, <= 256) */
     const float* w1;     /* H x 2 */
@@ -109,9 +114,8 @@ typedef struct {
     float b3;
     float in_shift[2], in_scale[2];
     float out_shift, out_scale;
-    int32_t max_newton;  /* seeded Newton iterations before the plain fallback (e.g. 3) */
-    int32_t output;      /* 0: the network predicts ln e (as configured);
-                            1: it predicts the bracket fraction (E - e) E / |M|^2, so e = E - y |M|^2 / E */
+    int32_t output;      /* 0: z = ln e;
+                            1: z = the bracket fraction (E - e) E / |M|^2, so e = E - z |M|^2 / E */
 } mf_surrogate;
 
 /* Create a handle for n_events independent grids (Sec. 2.1 problem statement,
@@ -161,12 +165,13 @@ int mf_batch_step(mf_grid_t g, const double* dt, int32_t nsteps, mf_stats* st);
  * EoS and dtype: U = 4 device arrays (E, Mx, My, Mz), prim = 5 device arrays
  * (e, p, vx, vy, vz).  iters_dev (nullable, int32 device array of n) receives
  * the root-finder iterations per state (0 for the closed form).  mode:
- * MF_C2P_PLAIN or MF_C2P_SEEDED (needs a surrogate).  Asynchronous. */
+ * MF_C2P_PLAIN (midpoint start, whether or not a seed is installed),
+ * MF_C2P_SEEDED (needs a surrogate) or MF_C2P_CONFORMAL.  Asynchronous. */
 int mf_con2prim(mf_grid_t g, const void* const U[4], void* const prim[5], int64_t n,
                 int32_t* iters_dev, int32_t mode);
 
 /* Counters of the last mf_con2prim call: out = (clamped |M|, bad states,
- * root-finder iterations, seeded solves restarted plain).  Synchronous. */
+ * root-finder iterations, seeded guesses outside the bracket).  Synchronous. */
 int mf_con2prim_stats(mf_grid_t g, int64_t out[4]);
 
 /* ---- the seed network's training kernels (BF16 matrix cores, FP32 accumulation)

@@ -71,7 +71,7 @@ struct Counts {
     uint32_t floor_ = 0;  // |M| clamped
     uint32_t bad = 0;     // E <= 0 or non-finite
     uint32_t iters = 0;   // root-finder iterations (table EoS)
-    uint32_t fallback = 0; // seeded solves that restarted from the plain bracket
+    uint32_t fallback = 0; // seeded solves whose guess lay outside the bracket
 };
 
 // ---------------------------------------------------------------------------
@@ -209,7 +209,6 @@ struct EosTable {
     const float* seed;   // [sg0][sg1] or nullptr (plain solve)
     int32_t sg0, sg1;
     float seed_lnE0, seed_inv_dlnE;  // grid origin and inverse spacing in ln E
-    int32_t max_newton;              // seeded Newton iterations before the plain restart
     int32_t seed_output;             // 0: grid holds ln e; 1: the bracket fraction (E - e) E / |M|^2
 
     __device__ __forceinline__ void eval(double e, double& p, double& dp) const
@@ -266,10 +265,11 @@ struct EosTable {
         dp = d00 * (r0.y - r1.y) + d10 * r0.z + d11 * r1.z;
     }
 
-    // Root e of g on the bracket, starting from e_start (inside the bracket).
-    __device__ __forceinline__ double solve(double E, double M2, double e_start, Counts& cnt) const
+    // Root e of g on the bracket [lo, E], starting from e_start (inside the
+    // bracket).  Newton steps that leave the shrinking bracket are replaced by
+    // bisection.
+    __device__ __forceinline__ double solve(double E, double M2, double lo, double e_start, Counts& cnt) const
     {
-        double lo = E - M2 * Math<double>::rcp(E);
         double hi = E;
         double e = e_start;
         for (int it = 0; it < max_iter; it++) {
@@ -295,40 +295,24 @@ struct EosTable {
         return e;
     }
 
-    // Seeded solve: unsafeguarded Newton from e0 for at most max_newton
-    // iterations; if e0 or an iterate leaves the bracket, or the run has not
-    // converged, restart the plain solve from the bracket midpoint.
-    __device__ __forceinline__ double solve_seeded(double E, double M2, double e0, int nmax, Counts& cnt) const
+    // Start of a seeded solve: the guess e0 if it lies strictly inside the
+    // bracket [lo, E], else the bracket midpoint (counted as a fallback).
+    __device__ __forceinline__ static double seeded_start(double E, double lo, double e0, Counts& cnt)
     {
-        const double lo = E - M2 * Math<double>::rcp(E);
-        const double hi = E;
-        if (e0 > lo && e0 < hi) {
-            double e = e0;
-            for (int it = 0; it < nmax; it++) {
-                double p, dp;
-                eval(e, p, dp);
-                const double iw = Math<double>::rcp(E + p);
-                const double g = (e - E) + M2 * iw;
-                const double gp = 1.0 - M2 * dp * iw * iw;
-                const double de = g * Math<double>::rcp(gp);
-                const double en = e - de;
-                cnt.iters++;
-                if (fabs(de) <= 1e-12 * e) return en;
-                if (!(en > lo && en < hi)) break;
-                e = en;
-            }
-        }
+        if (e0 > lo && e0 < E) return e0;
         cnt.fallback++;
-        return solve(E, M2, 0.5 * (lo + hi), cnt);
+        return 0.5 * (lo + E);
     }
 
-    // Bilinear read of the seed grid at (ln E, m); returns the guess e0.
-    __device__ __forceinline__ double seed_guess(double E, double M2) const
+    // Bilinear read of the seed grid at (ln E, m); q = |M|^2 / E.  Returns the guess e0.
+    __device__ __forceinline__ double seed_guess(double E, double M2, double q) const
     {
-        const float lnE = __builtin_amdgcn_logf((float)E) * 0.69314718f;
-        const float m = (float)(Math<double>::sqrt(M2) * Math<double>::rcp(E));
+        const float Ef = (float)E;
+        const float lnE = __builtin_amdgcn_logf(Ef) * 0.69314718f;
+        const float m = __builtin_amdgcn_sqrtf((float)M2) * __builtin_amdgcn_rcpf(Ef);
         float u = (lnE - seed_lnE0) * seed_inv_dlnE;
         float v = m * (float)(sg1 - 1);
+        // clamps also map NaN to 0 (fmaxf returns the other operand)
         u = fminf(fmaxf(u, 0.0f), (float)(sg0 - 1) - 1e-3f);
         v = fminf(fmaxf(v, 0.0f), (float)(sg1 - 1) - 1e-3f);
         const int i = (int)u, j = (int)v;
@@ -336,16 +320,17 @@ struct EosTable {
         const float* r0 = seed + (int64_t)i * sg1 + j;
         const float* r1 = r0 + sg1;
         const float y = (1.0f - fu) * ((1.0f - fv) * r0[0] + fv * r0[1]) + fu * ((1.0f - fv) * r1[0] + fv * r1[1]);
-        if (seed_output == 1) return E - (double)y * M2 * Math<double>::rcp(E);
+        if (seed_output == 1) return E - (double)y * q;
         return (double)__expf(y);
     }
 
     __device__ __forceinline__ double recover(double E, double M2, Counts& cnt) const
     {
         if (M2 == 0.0) return E;
-        if (seed) return solve_seeded(E, M2, seed_guess(E, M2), max_newton, cnt);
-        const double lo = E - M2 * Math<double>::rcp(E);
-        return solve(E, M2, 0.5 * (lo + E), cnt);
+        const double q = M2 * Math<double>::rcp(E);
+        const double lo = E - q;
+        const double e_start = seed ? seeded_start(E, lo, seed_guess(E, M2, q), cnt) : 0.5 * (lo + E);
+        return solve(E, M2, lo, e_start, cnt);
     }
 
     __device__ __forceinline__ bool fixup(double& E, double& Mx, double& My, double& Mz, double& M2,

@@ -300,10 +300,11 @@ __global__ void k_mlp_adam(float* __restrict__ P, const float* __restrict__ g, f
 
 // ---------------------------------------------------------------------------
 // Seeded con2prim over n states with the tabulated EoS.  mode 1: the initial
-// guess is exp(MLP(ln E, |M|/E)) evaluated on the matrix cores for the
-// wavefront's 64 states; mode 2: the conformal (p = e/3) closed form.  Then at
-// most max_newton unsafeguarded Newton steps, and the plain bracketed solve
-// if the guess or an iterate leaves the bracket or the steps do not converge.
+// guess comes from the MLP on (ln E, |M|/E), evaluated on the matrix cores
+// for the wavefront's 64 states (ln e, or the bracket fraction); mode 2: the
+// conformal (p = e/3) closed form.  The guess starts the same safeguarded
+// Newton solve as the plain one if it lies inside the bracket, else the solve
+// starts at the midpoint (counted as a fallback).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_con2prim_seeded(C2PArgs<double> a, EosTable eos, const float* __restrict__ P,
                                                          SeedNorm nrm, int mode)
@@ -341,15 +342,17 @@ __global__ __launch_bounds__(256) void k_con2prim_seeded(C2PArgs<double> a, EosT
     }
     double e = E;
     if (M2 != 0.0) {
+        const double q = M2 * Math<double>::rcp(E);
+        const double lo = E - q;
         double e0;
         if (mode == 1) {
             const double pred = (double)(y * nrm.out_scale + nrm.out_shift);
-            e0 = nrm.output == 1 ? E - pred * M2 / E : exp(pred);
+            e0 = nrm.output == 1 ? E - pred * q : exp(pred);
         } else {
-            const double c = 1.0 / 3.0, q = 1.0 + c;
-            e0 = E - 2.0 * M2 / (q * E + sqrt(q * q * E * E - 4.0 * c * M2));
+            const double c = 1.0 / 3.0, b = 1.0 + c;
+            e0 = E - 2.0 * M2 / (b * E + sqrt(b * b * E * E - 4.0 * c * M2));
         }
-        e = eos.solve_seeded(E, M2, e0, nrm.max_newton, cnt);
+        e = eos.solve(E, M2, lo, EosTable::seeded_start(E, lo, e0, cnt), cnt);
     }
     double p, dp;
     eos.eval(e, p, dp);

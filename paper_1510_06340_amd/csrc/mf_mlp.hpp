@@ -18,7 +18,6 @@ constexpr int kMlpParams = 2 * kMlpHidden + kMlpHidden + kMlpHidden * kMlpHidden
 struct SeedNorm {
     float in_shift[2], in_scale[2];  // x = ((ln E, |M|/E) - shift) * scale
     float out_shift, out_scale;      // prediction = y * scale + shift
-    int max_newton;
     int output;                      // 0: prediction = ln e; 1: = (E - e) E / |M|^2
 };
 

@@ -614,7 +614,6 @@ int install_seed(mf_grid_s* g, const mf_surrogate& s)
     }
     nrm.out_shift = s.out_shift;
     nrm.out_scale = s.out_scale;
-    nrm.max_newton = s.max_newton;
     nrm.output = s.output;
     int rc = g->alloc((void**)&g->seed_params, sizeof(float) * MF_MLP_PARAMS);
     if (!rc) rc = g->alloc((void**)&g->seed_grid, sizeof(float) * kSeedG0 * kSeedG1);
@@ -647,7 +646,6 @@ int install_seed(mf_grid_s* g, const mf_surrogate& s)
     t.sg1 = kSeedG1;
     t.seed_lnE0 = (float)kSeedLnLo;
     t.seed_inv_dlnE = (float)(1.0 / dl);
-    t.max_newton = nrm.max_newton;
     t.seed_output = nrm.output;
     return MF_OK;
 }
@@ -748,9 +746,9 @@ int mf_set_eos(mf_grid_t g, int32_t kind, double cs2, const double* e_tab, const
         if (i > 0 && (!(e_tab[i] > e_tab[i - 1]) || p_tab[i] < p_tab[i - 1]))
             return fail(MF_ERR_ARG, "table e must increase strictly and p must not decrease");
     }
-    if (s && (s->hidden != MF_MLP_HIDDEN || !s->w1 || !s->b1 || !s->w2 || !s->b2 || !s->w3 || s->max_newton < 1 ||
+    if (s && (s->hidden != MF_MLP_HIDDEN || !s->w1 || !s->b1 || !s->w2 || !s->b2 || !s->w3 ||
               (s->output != 0 && s->output != 1)))
-        return fail(MF_ERR_ARG, "the seed network must be 2-64-64-1 with all weights, max_newton >= 1, output 0 or 1");
+        return fail(MF_ERR_ARG, "the seed network must be 2-64-64-1 with all weights and output 0 or 1");
     std::vector<double> m;
     monotone_slopes(n_tab, e_tab, p_tab, m);
     std::vector<double> rec(4 * (size_t)n_tab);
@@ -1015,7 +1013,6 @@ int mf_con2prim(mf_grid_t g, const void* const U[4], void* const prim[5], int64_
         EosTable t = g->table;
         t.seed = nullptr;
         SeedNorm nrm = g->seed_norm;
-        if (!g->has_seed) nrm.max_newton = 3;
         e = con2prim_seeded(n, g->stream, a, t, g->seed_params, nrm, mode == MF_C2P_SEEDED ? 1 : 2);
     } else if (g->eos_kind == MF_EOS_TABLE) {
         C2PArgs<double> a;

@@ -49,7 +49,7 @@ class Surrogate(C.Structure):
     _fields_ = [("hidden", C.c_int32), ("w1", C.POINTER(C.c_float)), ("b1", C.POINTER(C.c_float)),
                 ("w2", C.POINTER(C.c_float)), ("b2", C.POINTER(C.c_float)), ("w3", C.POINTER(C.c_float)),
                 ("b3", C.c_float), ("in_shift", C.c_float * 2), ("in_scale", C.c_float * 2),
-                ("out_shift", C.c_float), ("out_scale", C.c_float), ("max_newton", C.c_int32),
+                ("out_shift", C.c_float), ("out_scale", C.c_float),
                 ("output", C.c_int32)]
 
 
@@ -223,7 +223,7 @@ class Grid:
         return list(ms), list(n)
 
     def con2prim_stats(self):
-        """Counters of the last con2prim call: (clamped, bad, iterations, seeded restarts)."""
+        """Counters of the last con2prim call: (clamped, bad, iterations, seeded guesses outside the bracket)."""
         out = (C.c_int64 * 4)()
         _check(lib().mf_con2prim_stats(self.h, out))
         return list(out)
@@ -248,7 +248,7 @@ class Grid:
 class SeedNetwork:
     """Host copy of the seed network's FP32 weights and normalisation (for mf_set_eos)."""
 
-    def __init__(self, params, in_shift, in_scale, out_shift, out_scale, max_newton=3, output=0):
+    def __init__(self, params, in_shift, in_scale, out_shift, out_scale, output=0):
         import numpy as np
         p = np.ascontiguousarray(params, dtype=np.float32)
         if p.size != MF_MLP_PARAMS:
@@ -260,7 +260,6 @@ class SeedNetwork:
         self.b3 = float(p[-1])
         self.in_shift, self.in_scale = [float(v) for v in in_shift], [float(v) for v in in_scale]
         self.out_shift, self.out_scale = float(out_shift), float(out_scale)
-        self.max_newton = int(max_newton)
         self.output = int(output)
 
     def struct(self) -> Surrogate:
@@ -271,7 +270,7 @@ class SeedNetwork:
         s.b3 = self.b3
         s.in_shift[:] = self.in_shift
         s.in_scale[:] = self.in_scale
-        s.out_shift, s.out_scale, s.max_newton = self.out_shift, self.out_scale, self.max_newton
+        s.out_shift, s.out_scale = self.out_shift, self.out_scale
         s.output = self.output
         return s
 

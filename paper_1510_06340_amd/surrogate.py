@@ -5,7 +5,7 @@
    advanced on the GPU; the cell states (E, |M|) of snapshots taken every few
    steps form the stream from which ``n_samples`` states with |M| > 0 are
    reservoir-sampled (random keys from a seeded generator, smallest keys kept).
-2. Labels: the plain bracketed-Newton con2prim (mf_con2prim, MF_C2P_PLAIN).
+2. Labels: e and p from the plain bracketed-Newton con2prim (mf_con2prim, MF_C2P_PLAIN).
 3. Network: 2 -> 64 -> 64 -> 1 tanh on x = ((ln E, |M|/E) - mean) / std,
    predicting the standardised ln e (as configured) or, optionally, the
    root's position in the bracket [E(1 - m^2), E]; trained with Adam on the mean squared
@@ -83,7 +83,7 @@ def collect_states(n_samples=1 << 22, seed=42, n=128, snap_every=6, steps=60):
 
 
 def label_states(E, Mabs, table=None):
-    """Plain bracketed-Newton con2prim of states (E, |M| along x): returns e (torch float64)."""
+    """Plain bracketed-Newton con2prim of states (E, |M| along x): returns (e, p) (torch float64)."""
     import torch
     table = I.crossover_table() if table is None else table
     n = E.numel()
@@ -94,7 +94,7 @@ def label_states(E, Mabs, table=None):
     g.con2prim(U, prim)
     torch.cuda.synchronize()
     g.free()
-    return prim[0]
+    return prim[0], prim[1]
 
 
 class Trained:
@@ -104,10 +104,9 @@ class Trained:
         self.history = history      # list of (epoch, train_loss, val_loss)
         self.output = output        # 0: ln e, 1: bracket fraction (E - e) E / |M|^2
 
-    def network(self, max_newton=3) -> mf.SeedNetwork:
+    def network(self) -> mf.SeedNetwork:
         n = self.norm
-        return mf.SeedNetwork(self.params, n["in_shift"], n["in_scale"], n["out_shift"], n["out_scale"], max_newton,
-                              self.output)
+        return mf.SeedNetwork(self.params, n["in_shift"], n["in_scale"], n["out_shift"], n["out_scale"], self.output)
 
     def predict_e(self, E, Mabs, y):
         """Guess e from the network output y (standardised)."""
@@ -119,15 +118,18 @@ class Trained:
         return torch.exp(pred)
 
 
-def train(E, Mabs, e, epochs=30, batch=4096, lr=2e-3, lr_min=2e-5, seed=0, val_frac=0.1, output=0):
+def train(E, Mabs, e, p, epochs=30, batch=4096, lr=2e-3, lr_min=2e-5, seed=0, val_frac=0.1, output=0):
     """Fit the seed from (ln E, |M|/E) with the matrix-core kernels; returns a Trained network.
 
-    output 0: the target is ln e (as configured); output 1: the target is the
-    position of the root in the bracket [E(1 - m^2), E], (E - e) E / |M|^2."""
+    (e, p) are the labels from label_states.  output 0: the target is ln e (as
+    configured); output 1: the target is the position of the root in the
+    bracket [E(1 - m^2), E], phi = (E - e) E / |M|^2.  At the root
+    E - e = |M|^2 / (E + p), so phi = E / (E + p), which is taken in that form
+    (no cancellation near rest)."""
     import torch
     x0 = torch.log(E)
     x1 = Mabs / E
-    y = torch.log(e) if output == 0 else (E - e) * E / (Mabs * Mabs)
+    y = torch.log(e) if output == 0 else E / (E + p)
     mu = [float(x0.mean()), float(x1.mean())]
     sd = [float(x0.std()), float(x1.std())]
     ym, ys = float(y.mean()), float(y.std())
@@ -171,7 +173,7 @@ def train(E, Mabs, e, epochs=30, batch=4096, lr=2e-3, lr_min=2e-5, seed=0, val_f
 
 
 def relative_error(trained: Trained, E, Mabs, e):
-    """|exp(prediction) - e| / e on the given states (via mf_mlp_forward)."""
+    """|guess - e| / e on the given states (network via mf_mlp_forward)."""
     import torch
     n = trained.norm
     X = torch.stack([(torch.log(E) - n["in_shift"][0]) * n["in_scale"][0],

@@ -95,17 +95,18 @@ def test_adam_step_matches_formula():
 @pytest.fixture(scope="module")
 def trained():
     E, M = surrogate.collect_states(n_samples=1 << 20, n=64, steps=30, snap_every=5)
-    e = surrogate.label_states(E, M)
-    net = surrogate.train(E, M, e, epochs=20, batch=4096)
-    frac = surrogate.train(E, M, e, epochs=20, batch=4096, output=1)
+    e, pr = surrogate.label_states(E, M)
+    net = surrogate.train(E, M, e, pr, epochs=20, batch=4096)
+    frac = surrogate.train(E, M, e, pr, epochs=20, batch=4096, output=1)
     return dict(E=E, M=M, e=e, net=net, frac=frac)
 
 
-def test_training_lowers_the_loss(trained):
-    h = trained["net"].history
+@pytest.mark.parametrize("which", ["net", "frac"])
+def test_training_lowers_the_loss(trained, which):
+    h = trained[which].history
     print("\nepoch, train loss, validation loss:", [(a, round(b, 6), round(c, 6)) for a, b, c in h[::4] + h[-1:]])
     assert h[-1][1] < 0.2 * h[0][1] and h[-1][2] < 0.2 * h[0][2]
-    err = surrogate.relative_error(trained["net"], trained["E"], trained["M"], trained["e"])
+    err = surrogate.relative_error(trained[which], trained["E"], trained["M"], trained["e"])
     print(f"relative error of the seed: median {float(err.median()):.2e}, 99% {float(err.quantile(0.99)):.2e}")
     assert float(err.median()) < 0.05
 
@@ -134,14 +135,14 @@ def test_seeded_con2prim_equals_plain(trained, which):
     """P13: every seeded solution equals the plain one to 1e-12 relative.
 
     The gain: near rest (|M|/E << 1) the bracket [E(1 - m^2), E] is so narrow
-    that its midpoint is already closer than any seed (the seed then leaves
-    the bracket and the solve restarts plain, which costs no Newton steps);
+    that its midpoint is already closer than a guess of ln e can be (the guess
+    then lies outside the bracket and the solve starts at the midpoint);
     where the flow is relativistic (m > 0.05) the root sits near 3/4 of the
     bracket, so the midpoint is off by about m^2/4: the network that predicts
     the root's position in the bracket ("frac") must then need fewer
     iterations than the midpoint start; the one predicting ln e ("net", the
     configured output) is reported."""
-    net = trained[which].network(max_newton=3)
+    net = trained[which].network()
     E, M = trained["E"], trained["M"]
     ep, itp, _, tp = run_c2p(E, M, mf.MF_C2P_PLAIN, net)
     es, its, sts, ts = run_c2p(E, M, mf.MF_C2P_SEEDED, net)
@@ -154,7 +155,7 @@ def test_seeded_con2prim_equals_plain(trained, which):
         assert rel <= 1e-12, rel
     mp, ms, mc = float(itp.float().mean()), float(its.float().mean()), float(itc.float().mean())
     print(f"\nall {E.numel()} states: mean Newton iterations plain {mp:.3f}, learned seed {ms:.3f} "
-          f"(restarts {sts[3]}), conformal {mc:.3f} (restarts {stc[3]}); "
+          f"(guesses outside the bracket {sts[3]}), conformal {mc:.3f} (outside {stc[3]}); "
           f"time ms plain {tp:.3f} seeded {ts:.3f} conformal {tc:.3f}")
     fast = (M / E) > 0.05
     sp, ss, sc = (float(x[fast].float().mean()) for x in (itp, its, itc))
@@ -164,9 +165,10 @@ def test_seeded_con2prim_equals_plain(trained, which):
         assert ss < sp
 
 
-def test_seeded_run_equals_plain_run(trained):
+@pytest.mark.parametrize("which", ["net", "frac"])
+def test_seeded_run_equals_plain_run(trained, which):
     """A crossover-EoS run with the learned seed (prediction grid in the sweeps) equals the plain run to 1e-10."""
-    net = trained["net"].network(max_newton=3)
+    net = trained[which].network()
     w = I.crossover_workloads(n_events=1, n=40, steps=5)[0]
     U = I.initial_state(w)
     Up, stp = gpu_run(w, U, eos_table=TABLE)
@@ -182,5 +184,5 @@ def test_seeded_run_equals_plain_run(trained):
     Uo, _ = oracle.step(oracle.Problem.from_workload(w, table=TABLE), U, w.dt, w.steps)
     assert max_rel_err(Us, Uo) <= 1e-10
     print(f"\nstep iterations: plain {stp['newton_iters']}, seeded {sts['newton_iters']} "
-          f"(restarts {sts['n_fallback']})")
+          f"(guesses outside the bracket {sts['n_fallback']})")
     assert sts["n_fallback"] > 0
