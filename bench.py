@@ -54,9 +54,9 @@ def bytes_per_cell_step(rk: int, elem: int) -> int:
     return passes * 4 * elem
 
 
-def cpu_baseline(w, U, budget_s: float):
+def cpu_baseline(w, U, budget_s: float, table=None):
     import oracle
-    prob = oracle.Problem.from_workload(w)
+    prob = oracle.Problem.from_workload(w, table=table)
     steps, t_total = 0, 0.0
     V = U
     while steps < 20:
@@ -185,6 +185,8 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=None, help="cells per axis (hotspot / jet)")
     ap.add_argument("--events", type=int, default=None, help="events (ensemble / crossover)")
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--eos", choices=["ideal", "table"], default="ideal",
+                    help="hotspot only: p = e/3, or the tabulated crossover EoS")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time (0 = skip)")
     ap.add_argument("--seg", type=int, nargs=3, default=None, help="x chunks per wavefront, y and z cells per thread")
     ap.add_argument("--block", type=int, default=256)
@@ -212,7 +214,15 @@ def main(argv=None):
     jet_x0 = None
     if args.workload == "hotspot":
         w = I.hotspot_workload(n=args.n or 256)
-        desc = (f"hotspot {w.n[0]}x{w.n[1]}x{w.n[2]} (40 seeded Gaussian hot spots, seed {w.seed}), p=e/3, "
+        eos_desc = "p=e/3"
+        if args.eos == "table":
+            if args.dtype != "f64":
+                print("bench.py: the tabulated EoS runs in FP64 only", file=sys.stderr)
+                return 2
+            table = I.crossover_table()
+            w.eos = I.EOS_TABLE
+            eos_desc = "tabulated crossover EoS"
+        desc = (f"hotspot {w.n[0]}x{w.n[1]}x{w.n[2]} (40 seeded Gaussian hot spots, seed {w.seed}), {eos_desc}, "
                 f"MC limiter, k={w.k}, RK{w.rk}, dt={w.dt:g}, outflow")
     elif args.workload == "jet":
         w = I.jet_workload(n=args.n or 512)
@@ -269,8 +279,11 @@ def main(argv=None):
         },
         "end_state": {"smax": st["smax"], "n_floor": st["n_floor"], "n_bad": st["n_bad"], "E_total": st["totals"][0]},
     }
+    if table is not None:
+        out["roofline"]["note"] = ("algorithmic flops counted as for p = e/3; the table lookups and Newton "
+                                   "iterations of the tabulated EoS are not counted")
     if args.cpu_budget > 0 and args.workload != "jet":
-        out["cpu_baseline"] = cpu_baseline(w, U, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(w, U, args.cpu_budget, table)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -184,8 +184,13 @@ template <typename T> struct EosIdeal {
 // ---------------------------------------------------------------------------
 // Tabulated p(e): monotone piecewise-cubic Hermite interpolation on nodes
 // e_i with node slopes m_i (Fritsch-Carlson), p = p_0 e / e_0 below the first
-// node and linear with the end slope above the last.  One 32-byte record per
-// node: (e_i, p_i, m_i, 1 / (e_{i+1} - e_i)).
+// node and linear with the end slope above the last.
+//
+// The table holds n + 1 pieces of 64 bytes, (lo, hi, x, w) and
+// (y, c1, c2, c3), with p(e) = y + t (c1 + t (c2 + t c3)), t = (e - x) w on
+// [lo, hi): piece 0 is the extrapolation below e_0, pieces 1 .. n-1 the
+// cubics between nodes (the Hermite cubic in powers of t), piece n the
+// extrapolation above e_{n-1}.  One piece is one lookup: two 32-byte loads.
 //
 // con2prim (Sec. 2.6): the fixed point v = |M| / (E + p(E - |M| v)) is the
 // root of g(e) = e - E + |M|^2 / (E + p(e)) on the bracket [E (1 - m^2), E],
@@ -196,85 +201,80 @@ template <typename T> struct EosIdeal {
 // ---------------------------------------------------------------------------
 struct EosTable {
     static constexpr int kWaves = 2;
-    const double4* rec;  // n records
-    int32_t n;
-    int32_t log_uniform; // index from log2(e) (then a +-1 fix-up); else bisection
+    const double4* rec;  // 2 (n + 1) records: piece k = rec[2k], rec[2k + 1]
+    int32_t n;           // nodes
+    int32_t log_uniform; // piece from log2(e) (then a fix-up); else bisection
     float lg0;           // log2 e_0
     float inv_dlg;       // (n - 1) / (log2 e_{n-1} - log2 e_0)
-    double e0, p0_e0;    // first node and p_0 / e_0
-    double elast, plast, mlast;
     int32_t max_iter;
-    // learned seed: predictions ln e of the MLP on a grid over (ln E, |M|/E),
+    // learned seed: predictions of the MLP on a grid over (ln E, |M|/E),
     // read by bilinear interpolation (the grid is filled by the MLP kernel)
     const float* seed;   // [sg0][sg1] or nullptr (plain solve)
     int32_t sg0, sg1;
     float seed_lnE0, seed_inv_dlnE;  // grid origin and inverse spacing in ln E
     int32_t seed_output;             // 0: grid holds ln e; 1: the bracket fraction (E - e) E / |M|^2
 
-    __device__ __forceinline__ void eval(double e, double& p, double& dp) const
+    // The piece of e (e >= 0): (lo, hi, x, w) in a, (y, c1, c2, c3) in b.
+    __device__ __forceinline__ void piece(double e, double4& a, double4& b) const
     {
-        if (!(e > e0)) {
-            p = p0_e0 * e;
-            dp = p0_e0;
-            return;
-        }
-        if (e >= elast) {
-            p = plast + mlast * (e - elast);
-            dp = mlast;
-            return;
-        }
-        int i;
-        double4 r0, r1;
+        int k;
         if (log_uniform) {
-            const float l = __builtin_amdgcn_logf((float)e);  // log2, about 1 ulp
-            i = (int)((l - lg0) * inv_dlg);
-            i = i < 0 ? 0 : (i > n - 2 ? n - 2 : i);
-            r0 = rec[i];
-            r1 = rec[i + 1];
-            if (e < r0.x && i > 0) {
-                i--;
-                r1 = r0;
-                r0 = rec[i];
-            } else if (e >= r1.x && i < n - 2) {
-                i++;
-                r0 = r1;
-                r1 = rec[i + 1];
+            float u = (__builtin_amdgcn_logf((float)e) - lg0) * inv_dlg;  // log2 (about 1 ulp)
+            u = fminf(fmaxf(u, -1.0f), (float)n);                          // also maps NaN to -1
+            k = (int)floorf(u) + 1;
+            k = k < 0 ? 0 : (k > n ? n : k);
+            a = rec[2 * k];
+            b = rec[2 * k + 1];
+            // the single-precision log can put e one piece off near a node
+            const bool off = (e < a.x) | (e >= a.y);
+            if (__any(off)) {
+                if (off) {
+                    while (k > 0 && e < rec[2 * k].x) k--;
+                    while (k < n && e >= rec[2 * k].y) k++;
+                    a = rec[2 * k];
+                    b = rec[2 * k + 1];
+                }
             }
         } else {
-            int lo = 0, hi = n - 1;
+            int lo = 0, hi = n + 1;  // rec[2 lo].x <= e < rec[2 hi].x
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
-                if (rec[mid].x <= e) lo = mid;
+                if (rec[2 * mid].x <= e) lo = mid;
                 else hi = mid;
             }
-            i = lo;
-            r0 = rec[i];
-            r1 = rec[i + 1];
+            k = lo;
+            a = rec[2 * k];
+            b = rec[2 * k + 1];
         }
-        const double h = r1.x - r0.x;
-        const double t = (e - r0.x) * r0.w;
-        const double t2 = t * t, t3 = t2 * t;
-        const double h00 = 2.0 * t3 - 3.0 * t2 + 1.0;
-        const double h10 = t3 - 2.0 * t2 + t;
-        const double h01 = -2.0 * t3 + 3.0 * t2;
-        const double h11 = t3 - t2;
-        p = h00 * r0.y + h10 * h * r0.z + h01 * r1.y + h11 * h * r1.z;
-        const double d00 = (6.0 * t2 - 6.0 * t) * r0.w;
-        const double d10 = 3.0 * t2 - 4.0 * t + 1.0;
-        const double d11 = 3.0 * t2 - 2.0 * t;
-        dp = d00 * (r0.y - r1.y) + d10 * r0.z + d11 * r1.z;
+    }
+
+    __device__ __forceinline__ void eval(double e, double& p, double& dp) const
+    {
+        double4 a, b;
+        piece(e, a, b);
+        const double t = (e - a.z) * a.w;
+        p = fma(t, fma(t, fma(t, b.w, b.z), b.y), b.x);
+        dp = a.w * fma(t, fma(t, 3.0 * b.w, 2.0 * b.z), b.y);
     }
 
     // Root e of g on the bracket [lo, E], starting from e_start (inside the
-    // bracket).  Newton steps that leave the shrinking bracket are replaced by
-    // bisection.
-    __device__ __forceinline__ double solve(double E, double M2, double lo, double e_start, Counts& cnt) const
+    // bracket), with p and dp/de at the root.  Newton steps that leave the
+    // shrinking bracket are replaced by bisection.  At rest (M2 = 0) the root
+    // is E and no iteration is counted.  On convergence p(e) is carried to the
+    // accepted iterate to first order (the remainder is O(de^2) with
+    // |de| <= 1e-12 e, far below rounding), so the root costs no extra lookup.
+    __device__ __forceinline__ double solve(double E, double M2, double lo, double e_start, double& p, double& dp,
+                                            Counts& cnt) const
     {
         double hi = E;
-        double e = e_start;
+        double e = M2 == 0.0 ? E : e_start;
+        bool done = false;
         for (int it = 0; it < max_iter; it++) {
-            double p, dp;
             eval(e, p, dp);
+            if (M2 == 0.0) {
+                done = true;
+                break;
+            }
             const double iw = Math<double>::rcp(E + p);
             const double g = (e - E) + M2 * iw;
             const double gp = 1.0 - M2 * dp * iw * iw;
@@ -284,7 +284,9 @@ struct EosTable {
             // converged: accept the (tiny) Newton correction before any bracket test,
             // which could otherwise reject an iterate sitting on the bracket edge
             if (fabs(de) <= 1e-12 * e) {
+                p = p - dp * de;
                 e = en;
+                done = true;
                 break;
             }
             if (g > 0.0) hi = e;
@@ -292,6 +294,7 @@ struct EosTable {
             if (!(en > lo && en < hi)) en = 0.5 * (lo + hi);
             e = en;
         }
+        if (!done) eval(e, p, dp);  // iteration cap reached
         return e;
     }
 
@@ -324,13 +327,14 @@ struct EosTable {
         return (double)__expf(y);
     }
 
-    __device__ __forceinline__ double recover(double E, double M2, Counts& cnt) const
+    // e, p and dp/de of a state with |M|^2 = M2 (E > 0, |M| < E).
+    __device__ __forceinline__ double recover(double E, double M2, double& p, double& dp, Counts& cnt) const
     {
-        if (M2 == 0.0) return E;
         const double q = M2 * Math<double>::rcp(E);
         const double lo = E - q;
-        const double e_start = seed ? seeded_start(E, lo, seed_guess(E, M2, q), cnt) : 0.5 * (lo + E);
-        return solve(E, M2, lo, e_start, cnt);
+        double e_start = 0.5 * (lo + E);
+        if (seed && M2 != 0.0) e_start = seeded_start(E, lo, seed_guess(E, M2, q), cnt);
+        return solve(E, M2, lo, e_start, p, dp, cnt);
     }
 
     __device__ __forceinline__ bool fixup(double& E, double& Mx, double& My, double& Mz, double& M2,
@@ -350,18 +354,34 @@ struct EosTable {
         return true;
     }
 
+    // Guards for every lane of the wavefront at once: states that need one
+    // are fixed (or replaced by a harmless state at rest and flagged) inside a
+    // wave-uniform branch, so the solve below runs once for all lanes.
+    __device__ __forceinline__ bool guard(double& E, double& Mx, double& My, double& Mz, double& M2,
+                                          Counts& cnt) const
+    {
+        const double Mlim = mmax<double>() * E;
+        const bool ok = (E > 0.0) & (E <= big_value<double>()) & (M2 <= Mlim * Mlim);
+        bool live = true;
+        if (__any(!ok)) {
+            if (!ok) {
+                live = fixup(E, Mx, My, Mz, M2, cnt);
+                if (!live) {
+                    E = 1.0; Mx = 0.0; My = 0.0; Mz = 0.0; M2 = 0.0;
+                }
+            }
+        }
+        return live;
+    }
+
     template <int D>
     __device__ __forceinline__ void flux(const double u[4], double F[4], Counts& cnt) const
     {
         double E = u[0], Mx = u[1], My = u[2], Mz = u[3];
         double M2 = Mx * Mx + My * My + Mz * Mz;
-        if (!fixup(E, Mx, My, Mz, M2, cnt)) {
-            F[0] = 0.0; F[1] = 0.0; F[2] = 0.0; F[3] = 0.0;
-            return;
-        }
-        const double e = recover(E, M2, cnt);
+        const bool live = guard(E, Mx, My, Mz, M2, cnt);
         double p, dp;
-        eval(e, p, dp);
+        recover(E, M2, p, dp, cnt);
         const double w = E + p;
         const double MD = (D == 0) ? Mx : ((D == 1) ? My : Mz);
         const double vD = MD * Math<double>::rcp(w);
@@ -370,6 +390,9 @@ struct EosTable {
         F[2] = My * vD;
         F[3] = Mz * vD;
         F[1 + D] = F[1 + D] + p;
+        if (!live) {
+            F[0] = 0.0; F[1] = 0.0; F[2] = 0.0; F[3] = 0.0;
+        }
     }
 
     __device__ __forceinline__ void prim(const double u[4], double& e, double& p, double v[3], double& cs2,
@@ -381,14 +404,14 @@ struct EosTable {
             e = 0.0; p = 0.0; v[0] = 0.0; v[1] = 0.0; v[2] = 0.0; cs2 = 0.0;
             return;
         }
-        e = recover(E, M2, cnt);
         double dp;
-        eval(e, p, dp);
+        e = recover(E, M2, p, dp, cnt);
         const double iw = Math<double>::rcp(E + p);
         v[0] = Mx * iw; v[1] = My * iw; v[2] = Mz * iw;
         cs2 = dp;
     }
 };
+
 
 // ---------------------------------------------------------------------------
 // Slope limiters (Sec. 2.5) in the two-argument form phi(a, b) = xi(b/a) a,

@@ -340,10 +340,10 @@ __global__ __launch_bounds__(256) void k_con2prim_seeded(C2PArgs<double> a, EosT
         __syncthreads();
         y = sy[w][l];
     }
-    double e = E;
+    const double q = M2 * Math<double>::rcp(E);
+    const double lo = E - q;
+    double e_start = E;
     if (M2 != 0.0) {
-        const double q = M2 * Math<double>::rcp(E);
-        const double lo = E - q;
         double e0;
         if (mode == 1) {
             const double pred = (double)(y * nrm.out_scale + nrm.out_shift);
@@ -352,11 +352,11 @@ __global__ __launch_bounds__(256) void k_con2prim_seeded(C2PArgs<double> a, EosT
             const double c = 1.0 / 3.0, b = 1.0 + c;
             e0 = E - 2.0 * M2 / (b * E + sqrt(b * b * E * E - 4.0 * c * M2));
         }
-        e = eos.solve(E, M2, lo, EosTable::seeded_start(E, lo, e0, cnt), cnt);
+        e_start = EosTable::seeded_start(E, lo, e0, cnt);
     }
     double p, dp;
-    eos.eval(e, p, dp);
-    const double iw = 1.0 / (E + p);
+    const double e = eos.solve(E, M2, lo, e_start, p, dp, cnt);
+    const double iw = Math<double>::rcp(E + p);
     if (valid) {
         if (ok) {
             a.prim[0][i] = e; a.prim[1][i] = p;
