@@ -78,11 +78,11 @@ __device__ __forceinline__ void flush_stats(unsigned long long* st, const Counts
 
 // Output of one cell of an axis sweep: write or accumulate L, or (last axis)
 // add the source, apply the Runge-Kutta combine and track the max speed.
-// uin = U[cell] of the stage input, Lp = L so far, ub = RK base state.
+// uin = U[cell] of the stage input, Lp = L so far, ub = RK base state,
+// SE = energy source of the cell (jet only; jet_source below).
 template <typename T, bool JET, class Eos>
 __device__ __forceinline__ void emit_cell(const SweepArgs<T>& a, const Eos& eos, int64_t ij, const T uin[4],
-                                          const T Ld[4], const T Lp[4], const T ub[4], const double pos[3],
-                                          T& smax)
+                                          const T Ld[4], const T Lp[4], const T ub[4], T SE, T& smax)
 {
     if (a.mode == SW_WRITE) {
 #pragma unroll
@@ -98,13 +98,6 @@ __device__ __forceinline__ void emit_cell(const SweepArgs<T>& a, const Eos& eos,
 #pragma unroll
     for (int c = 0; c < 4; c++) Lt[c] = Lp[c] + Ld[c];
     if constexpr (JET) {
-        // S = v dE/dx G_sigma(x - x_jet(t)) (1, v, 0, 0) at the cell centre
-        const double xj = a.jet_pos[0] + (a.t_ptr ? a.jet_v * (*a.t_ptr + a.t_off) : 0.0);
-        const T x = T(pos[0] - xj);
-        const T y = T(pos[1] - a.jet_pos[1]);
-        const T z = T(pos[2] - a.jet_pos[2]);
-        const T G = T(a.jet_norm) * exp(-(x * x + y * y + z * z) * T(a.jet_inv2s2));
-        const T SE = T(a.jet_ve) * G;
         Lt[0] = Lt[0] + SE;
         Lt[1] = Lt[1] + T(a.jet_v) * SE;
     }
@@ -132,6 +125,22 @@ __device__ __forceinline__ void emit_cell(const SweepArgs<T>& a, const Eos& eos,
         eos.prim(o, e, p, v, cs2, cs);
         smax = fmax(smax, max_speed(v, cs2));
     }
+}
+
+// Jet energy source S_E = v dE/dx G_sigma(x - x_jet(t)) at a cell centre at
+// squared distance r2 from the jet (the momentum source is v S_E).  Where the
+// exponent is below -746 the exponential is exactly 0 in FP64 (and FP32), so
+// wavefronts far from the jet skip it.
+template <typename T>
+__device__ __forceinline__ T jet_source(const SweepArgs<T>& a, double r2)
+{
+    const double arg = r2 * a.jet_inv2s2;
+    const bool near = arg < 746.0;
+    T SE = T(0);
+    if (__any(near)) {
+        if (near) SE = T(a.jet_ve) * (T(a.jet_norm) * exp(-T(arg)));
+    }
+    return SE;
 }
 
 // Ghost cells along a line of N cells: outflow copies the edge cell, periodic
@@ -186,6 +195,15 @@ __device__ __forceinline__ void sweep_line(const SweepArgs<T>& a, const Eos& eos
     // and (from j = s0-1 on) solves interface j+1/2; cells are written
     // from j = s0 on.  Warm-up and body share one instance of the code,
     // so results do not depend on the segmentation.
+    // jet source (z sweep): squared distance from the jet in the (x, y) plane of this line
+    double jet_dxy2 = 0.0;
+    if constexpr (JET && D == 2) {  // the line index runs over (x, y)
+        const double xj = a.jet_pos[0] + (a.t_ptr ? a.jet_v * (*a.t_ptr + a.t_off) : 0.0);
+        const double x = a.origin[0] + (i_f + 0.5) * a.dx[0] - xj;
+        const double y = a.origin[1] + (i_s + 0.5) * a.dx[1] - a.jet_pos[1];
+        jet_dxy2 = x * x + y * y;
+    }
+
     T w0[4], w1[4], w2[4];
     T ULt[4], URt[4], URp[4], Fp[4], Fn[4];
     load4(a.u, cell(s0 - 2), w1);
@@ -196,6 +214,14 @@ __device__ __forceinline__ void sweep_line(const SweepArgs<T>& a, const Eos& eos
         load4(a.u, cell(j + 2), w2);
         const int64_t ij = base + (int64_t)j * sd;
         const bool body = j >= s0;
+        // the jet source of cell j, evaluated here where few values are live
+        T SE = T(0);
+        if constexpr (JET && D == 2) {
+            if (body) {
+                const double z = a.origin[2] + (j + 0.5) * a.dx[2] - a.jet_pos[2];
+                SE = jet_source(a, jet_dxy2 + z * z);
+            }
+        }
 
         // cell j+1; counted once over all segments of the line (cells -1..N)
         Counts ch;
@@ -222,20 +248,22 @@ __device__ __forceinline__ void sweep_line(const SweepArgs<T>& a, const Eos& eos
         if (a.mode == SW_FINAL && a.kind != RK_FIRST) load4(a.u0, ij, ub);
 #pragma unroll
         for (int c = 0; c < 4; c++) Ld[c] = -(Fn[c] - Fp[c]) * a.ac.inv_dx;
-        double pos[3] = {0.0, 0.0, 0.0};
-        if constexpr (JET && D == 2) {  // z sweep: the line index runs over (x, y)
-            pos[0] = a.origin[0] + (i_f + 0.5) * a.dx[0];
-            pos[1] = a.origin[1] + (i_s + 0.5) * a.dx[1];
-            pos[2] = a.origin[2] + (j + 0.5) * a.dx[2];
-        }
-        emit_cell<T, JET>(a, eos, ij, w0, Ld, Lp, ub, pos, smax);
+        emit_cell<T, JET>(a, eos, ij, w0, Ld, Lp, ub, SE, smax);
 #pragma unroll
         for (int c = 0; c < 4; c++) Fp[c] = Fn[c];
     }
 }
 
+// Waves per SIMD the register budget is sized for.  The jet source adds a
+// few live values to the z sweep, which at 4 waves would spill.
+template <class Eos, bool JET>
+constexpr int sweep_waves()
+{
+    return JET && Eos::kWaves > 3 ? 3 : Eos::kWaves;
+}
+
 template <typename T, int D, int LIM, class Eos, bool JET>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Eos::kWaves))) void k_sweep(SweepArgs<T> a, Eos eos)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_waves<Eos, JET>()))) void k_sweep(SweepArgs<T> a, Eos eos)
 {
     const int64_t line = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     Counts cnt;
@@ -309,8 +337,7 @@ __device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& e
                 for (int c = 0; c < 4; c++) Ld[c] = -(F[c] - Fl[c]) * a.ac.inv_dx;
                 if (a.mode != SW_WRITE) load4((const T* const*)a.L, ij, Lp);
                 if (a.mode == SW_FINAL && a.kind != RK_FIRST) load4(a.u0, ij, ub);
-                const double pos[3] = {0.0, 0.0, 0.0};
-                emit_cell<T, false>(a, eos, ij, w0, Ld, Lp, ub, pos, smax);
+                emit_cell<T, false>(a, eos, ij, w0, Ld, Lp, ub, T(0), smax);
             }
 #pragma unroll
             for (int c = 0; c < 4; c++) {
@@ -347,7 +374,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Eos::kWaves
 // per-event kernels.
 // ---------------------------------------------------------------------------
 template <typename T, int D, int LIM, class Eos, bool JET>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Eos::kWaves)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_waves<Eos, JET>())))
 void k_batch_sweep(const SweepArgs<T>* __restrict__ tab, const int64_t* __restrict__ tile_start, int ne,
                    unsigned int* counter, Eos eos)
 {
