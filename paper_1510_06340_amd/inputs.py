@@ -147,6 +147,29 @@ def shock_tube_energy(n, dx, xlo, e_left=10.0, e_right=1.0) -> np.ndarray:
     return np.broadcast_to(row, (nz, ny, nx)).copy()
 
 
+def hubble_state(n, dx, xlo, t0=2.0, tau0=4.0, e0=1.0, cs2=1.0 / 3.0, edge=0.5) -> np.ndarray:
+    """Hubble-like expansion (Sec. 3.2, the spherically symmetric test): v = r / t0 and
+    e = e0 (tau0 / sqrt(t0^2 - r^2))^(3 (1 + cs2)) for r < t0 - edge, vacuum (e = v = 0)
+    outside; conserved state (4, nz, ny, nx) at the cell centres."""
+    nx, ny, nz = n
+    x = cell_centres(nx, dx[0], xlo[0])[None, None, :]
+    y = cell_centres(ny, dx[1], xlo[1])[None, :, None]
+    z = cell_centres(nz, dx[2], xlo[2])[:, None, None]
+    r2 = x * x + y * y + z * z
+    inside = r2 < (t0 - edge) ** 2
+    tau = np.sqrt(np.where(inside, t0 * t0 - r2, 1.0))
+    e = np.where(inside, e0 * (tau0 / tau) ** (3.0 * (1.0 + cs2)), 0.0)
+    p = cs2 * e
+    g2 = np.where(inside, 1.0 / (1.0 - r2 / (t0 * t0)), 1.0)
+    w = (e + p) * g2
+    U = np.zeros((4, nz, ny, nx))
+    U[0] = w - p
+    U[1] = np.where(inside, w * x / t0, 0.0)
+    U[2] = np.where(inside, w * y / t0, 0.0)
+    U[3] = np.where(inside, w * z / t0, 0.0)
+    return U
+
+
 def at_rest(e: np.ndarray) -> np.ndarray:
     """Conserved state of fluid at rest: (E, Mx, My, Mz) = (e, 0, 0, 0), shape (4, ...)."""
     U = np.zeros((4,) + e.shape)
@@ -260,10 +283,22 @@ def crossover_workloads(n_events: int = 32, base_seed: int = 2000, n: int = 192,
                      seed=base_seed + j) for j in range(n_events)]
 
 
+def hubble_workload(n: int = 120, dx: float = 0.1, dt: float = 0.03, steps: int = 20,
+                    limiter: int = LIM_MINMOD, k: int = 4, rk: int = 3) -> Workload:
+    """The paper's Hubble-like expansion test (Sec. 3.2 and its parameter table): 120^3
+    cells of 0.1 centred on the origin, dt = 0.03, e0 = 1, tau0 = 4, t0 = 2, p = e/3,
+    vacuum beyond r = t0 - 0.5; RK3 and 4 MUSTA stages as in the paper's experiments."""
+    return Workload("hubble", (n, n, n), (dx, dx, dx), (-0.5 * n * dx,) * 3, (BC_OUTFLOW,) * 3,
+                    limiter, k, rk, dt, steps, extra=dict(t0=2.0, tau0=4.0, e0=1.0, edge=0.5))
+
+
 def initial_state(w: Workload) -> np.ndarray:
     """Conserved FP64 state (4, nz, ny, nx) for a workload."""
     if w.name == "shock":
         return at_rest(shock_tube_energy(w.n, w.dx, w.xlo))
+    if w.name == "hubble":
+        x = w.extra
+        return hubble_state(w.n, w.dx, w.xlo, x["t0"], x["tau0"], x["e0"], w.cs2, x["edge"])
     ev = draw_event(w.seed, draw_sizes=(w.name == "ensemble"), draw_jet=(w.jet is not None))
     return at_rest(hotspot_energy(w.n, w.dx, w.xlo, ev))
 

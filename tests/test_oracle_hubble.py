@@ -1,0 +1,53 @@
+"""The Hubble-like expansion (Sec. 3.2): the only exact 3-D solution with flow.
+
+The oracle, run with the paper's experimental setting (RK3, 4 MUSTA stages,
+minmod) from the exact state at t0 = 2 with vacuum beyond r = 1.5, must follow
+the closed form e = e0 (tau0 / sqrt(t^2 - r^2))^4, v = r / t in the central
+region, and its error must fall about linearly as dx and dt are halved (the
+Hancock half step inside every Runge-Kutta stage makes the step first order
+in time).  A wrong sign or a dropped term in any axis' flux breaks the
+spherical expansion and fails this.
+"""
+import numpy as np
+
+from oracle import hubble
+from paper_1510_06340_amd import inputs as I
+
+
+def central_errors(ora, n, dx, dt, steps, lim=I.LIM_MINMOD):
+    w = I.hubble_workload(n=n, dx=dx, dt=dt, steps=steps, limiter=lim)
+    U = I.initial_state(w)
+    prob = ora.Problem.from_workload(w)
+    V, st = ora.step(prob, U, w.dt, w.steps, 2.0)
+    prim, _ = ora.con2prim(prob, V)
+    xs = I.cell_centres(n, dx, w.xlo[0])
+    r = np.sqrt(xs[:, None, None] ** 2 + xs[None, :, None] ** 2 + xs[None, None, :] ** 2)
+    sel = r < 0.6
+    ee, ve = hubble.exact(r[sel], 2.0 + steps * dt)
+    e = prim[0][sel]
+    v = np.sqrt(prim[2][sel] ** 2 + prim[3][sel] ** 2 + prim[4][sel] ** 2)
+    return float((np.abs(e - ee) / ee).max()), float(np.abs(v - ve).max()), st
+
+
+def test_hubble_expansion_follows_exact_solution(ora):
+    e1, v1, st1 = central_errors(ora, 32, 0.1, 0.03, 10)
+    e2, v2, _ = central_errors(ora, 64, 0.05, 0.015, 20)
+    print(f"\ncentral e error {e1:.2e} -> {e2:.2e}, v error {v1:.2e} -> {v2:.2e}")
+    assert e1 < 0.025 and v1 < 5e-3
+    assert e1 / e2 > 1.8 and v1 / v2 > 1.8
+    assert st1["n_bad"] > 0   # the vacuum is evaluated as the zero state
+
+
+def test_hubble_initial_state_is_the_exact_solution():
+    w = I.hubble_workload(n=24, dx=0.1)
+    U = I.initial_state(w)
+    xs = I.cell_centres(24, 0.1, w.xlo[0])
+    r = np.sqrt(xs[:, None, None] ** 2 + xs[None, :, None] ** 2 + xs[None, None, :] ** 2)
+    inside = r < 1.5
+    e, v = hubble.exact(r[inside], 2.0)
+    # E = (e + p) g^2 - p and |M| = (e + p) g^2 v with p = e / 3
+    g2 = 1.0 / (1.0 - v * v)
+    np.testing.assert_allclose(U[0][inside], (4.0 / 3.0) * e * g2 - e / 3.0, rtol=1e-14)
+    Mabs = np.sqrt((U[1:] ** 2).sum(0))[inside]
+    np.testing.assert_allclose(Mabs, (4.0 / 3.0) * e * g2 * v, rtol=1e-14, atol=1e-14)
+    assert np.all(U[:, ~inside] == 0.0)
