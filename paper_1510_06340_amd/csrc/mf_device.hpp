@@ -266,35 +266,34 @@ struct EosTable {
     __device__ __forceinline__ double solve(double E, double M2, double lo, double e_start, double& p, double& dp,
                                             Counts& cnt) const
     {
-        double hi = E;
         double e = M2 == 0.0 ? E : e_start;
-        bool done = false;
-        for (int it = 0; it < max_iter; it++) {
-            eval(e, p, dp);
-            if (M2 == 0.0) {
-                done = true;
-                break;
+        eval(e, p, dp);
+        if (__any(M2 != 0.0)) {  // wavefronts entirely at rest are done
+            if (M2 != 0.0) {
+                double hi = E;
+                for (int it = 1;; it++) {
+                    const double iw = Math<double>::rcp(E + p);
+                    const double g = (e - E) + M2 * iw;
+                    const double gp = 1.0 - M2 * dp * iw * iw;
+                    const double de = g * Math<double>::rcp(gp);
+                    double en = e - de;
+                    cnt.iters++;
+                    // converged: accept the (tiny) Newton correction before any bracket test,
+                    // which could otherwise reject an iterate sitting on the bracket edge
+                    if (fabs(de) <= 1e-12 * e) {
+                        p = p - dp * de;
+                        e = en;
+                        break;
+                    }
+                    if (g > 0.0) hi = e;
+                    else lo = e;
+                    if (!(en > lo && en < hi)) en = 0.5 * (lo + hi);
+                    e = en;
+                    eval(e, p, dp);
+                    if (it >= max_iter) break;  // iteration cap
+                }
             }
-            const double iw = Math<double>::rcp(E + p);
-            const double g = (e - E) + M2 * iw;
-            const double gp = 1.0 - M2 * dp * iw * iw;
-            const double de = g * Math<double>::rcp(gp);
-            double en = e - de;
-            cnt.iters++;
-            // converged: accept the (tiny) Newton correction before any bracket test,
-            // which could otherwise reject an iterate sitting on the bracket edge
-            if (fabs(de) <= 1e-12 * e) {
-                p = p - dp * de;
-                e = en;
-                done = true;
-                break;
-            }
-            if (g > 0.0) hi = e;
-            else lo = e;
-            if (!(en > lo && en < hi)) en = 0.5 * (lo + hi);
-            e = en;
         }
-        if (!done) eval(e, p, dp);  // iteration cap reached
         return e;
     }
 
@@ -330,10 +329,13 @@ struct EosTable {
     // e, p and dp/de of a state with |M|^2 = M2 (E > 0, |M| < E).
     __device__ __forceinline__ double recover(double E, double M2, double& p, double& dp, Counts& cnt) const
     {
-        const double q = M2 * Math<double>::rcp(E);
-        const double lo = E - q;
-        double e_start = 0.5 * (lo + E);
-        if (seed && M2 != 0.0) e_start = seeded_start(E, lo, seed_guess(E, M2, q), cnt);
+        double lo = E, e_start = E;
+        if (__any(M2 != 0.0)) {  // wavefronts entirely at rest need no bracket
+            const double q = M2 * Math<double>::rcp(E);
+            lo = E - q;
+            e_start = 0.5 * (lo + E);
+            if (seed && M2 != 0.0) e_start = seeded_start(E, lo, seed_guess(E, M2, q), cnt);
+        }
         return solve(E, M2, lo, e_start, p, dp, cnt);
     }
 
