@@ -68,6 +68,18 @@ def test_shock_tube_full_config_parity():
     assert st["steps"] == 100 and st["t"] == pytest.approx(3.0)
 
 
+@pytest.mark.parametrize("lim", range(6))
+def test_shock_tube_paper_setting(lim):
+    """The paper's experimental setting (RK3, 4 MUSTA stages) on the shock tube, every limiter, 100 steps."""
+    w = I.shock_workload(ny=4, nz=4, limiter=lim, k=4, rk=3)
+    U = I.initial_state(w)
+    Ug, st = gpu_run(w, U)
+    Uo, sto = oracle_run(w, U)
+    assert max_rel_err(Ug, Uo) <= TOL64
+    assert np.all(Ug == Ug[:, :1, :1, :])
+    assert st["n_floor"] == sto["n_floor"] and st["n_bad"] == sto["n_bad"]
+
+
 @pytest.mark.parametrize("bc", [I.BC_OUTFLOW, I.BC_PERIODIC])
 def test_hotspot_parity_ragged_grid(bc):
     """Hot spots on a 67x45x38 grid (ragged against every segment and block shape), MC, k = 3."""

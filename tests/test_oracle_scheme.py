@@ -264,3 +264,37 @@ def test_linear_table_step_matches_ideal(ora):
     a, _ = run(ora, ora.Problem.from_workload(w, table=(e_t, e_t / 3.0)), U, w.dt, 2)
     b, _ = run(ora, ora.Problem.from_workload(w), U, w.dt, 2)
     np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-13)
+
+
+def test_limiter_comparison_on_the_shock_tube(ora):
+    """The paper's limiter comparison (Sec. 3, shock-tube figures) in its experimental
+    setting (RK3, 4 MUSTA stages), against the exact solution at t = 3.
+
+    Qualitatively as the paper reports: without a limiter the profile oscillates
+    most (largest total variation and velocity overshoot); superbee is the most
+    compressive (smallest L1 error) but oscillates; minmod and van Albada stay
+    closest to the analytic solution (least total variation and overshoot)."""
+    names = ["none", "minmod", "superbee", "MC", "van Leer", "van Albada"]
+    res = {}
+    ex = None
+    for lim in range(6):
+        w = I.shock_workload(ny=1, nz=1, limiter=lim, k=4, rk=3)
+        prob = ora.Problem.from_workload(w)
+        V, _ = ora.step(prob, I.initial_state(w), w.dt, w.steps, 0.0)
+        prim, _ = ora.con2prim(prob, V)
+        x = I.cell_centres(w.n[0], w.dx[0], w.xlo[0])
+        ex = ShockTube().sample(x, 3.0)
+        e, v = prim[0].ravel(), prim[2].ravel()
+        res[names[lim]] = (np.abs(e - ex[0]).sum() * w.dx[0], np.abs(np.diff(e)).sum(), v.max() - ex[1].max())
+    tv_exact = np.abs(np.diff(ex[0])).sum()
+    print("\nlimiter: L1(e), TV(e) (exact %.3f), v overshoot" % tv_exact)
+    for k, (l1, tv, ov) in res.items():
+        print(f"  {k:10s} {l1:.4f} {tv:.3f} {ov:+.4f}")
+    tv = {k: r[1] for k, r in res.items()}
+    ov = {k: r[2] for k, r in res.items()}
+    l1 = {k: r[0] for k, r in res.items()}
+    assert max(tv, key=tv.get) == "none" and max(ov, key=ov.get) == "none"
+    assert min(l1, key=l1.get) == "superbee" and max(l1, key=l1.get) == "minmod"
+    assert sorted(tv, key=tv.get)[:2] == ["minmod", "van Albada"]
+    assert sorted(ov, key=ov.get)[:2] in (["minmod", "van Albada"], ["van Albada", "minmod"])
+    assert tv["superbee"] > tv["van Leer"] > tv["van Albada"] > tv_exact
