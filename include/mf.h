@@ -63,6 +63,9 @@ enum mf_c2p_mode {
 };
 
 #define MF_FLAG_STRICT 1u  /* mf_step fails on unphysical states or alpha*Courant > 1 */
+#define MF_FLAG_PREDICTOR_ALPHA 2u  /* ablation of the MUSTA predictor coefficient: alpha dt/dx
+                                       instead of dt/dx as printed in Sec. 2.4 (the FORCE
+                                       fluxes use alpha dt/dx either way) */
 
 typedef struct mf_grid_s* mf_grid_t;
 

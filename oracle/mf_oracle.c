@@ -66,6 +66,8 @@ typedef struct {
     double jet_v;       /* jet speed along +x */
     double jet_dedx;    /* deposited dE/dx */
     double jet_sigma;   /* Gaussian width of the deposition */
+    int32_t predictor_alpha; /* 1: alpha dt/dx in the MUSTA predictor (the alternative
+                                reading of Sec. 2.4; 0: dt/dx as printed) */
 } ora_params;
 
 typedef struct {
@@ -326,6 +328,7 @@ static void musta(const ora_params* P, int d, double lam, const double UL0[4],
 {
     double UL[4], UR[4], FL[4], FR[4], Us[4], Flw[4], Flf[4];
     const double alpha = P->alpha;
+    const double lp = P->predictor_alpha ? alpha * lam : lam;  /* predictor coefficient */
     for (int c = 0; c < 4; c++) { UL[c] = UL0[c]; UR[c] = UR0[c]; }
     for (int l = 1; l <= P->k; l++) {
         flux(P, d, UL, FL, cnt);
@@ -341,8 +344,8 @@ static void musta(const ora_params* P, int d, double lam, const double UL0[4],
         for (int c = 0; c < 4; c++) Fh[c] = 0.5 * (Flw[c] + Flf[c]);
         if (l < P->k) {
             for (int c = 0; c < 4; c++) {
-                UL[c] = UL[c] - lam * (Fh[c] - FL[c]);
-                UR[c] = UR[c] - lam * (FR[c] - Fh[c]);
+                UL[c] = UL[c] - lp * (Fh[c] - FL[c]);
+                UR[c] = UR[c] - lp * (FR[c] - Fh[c]);
             }
         }
     }

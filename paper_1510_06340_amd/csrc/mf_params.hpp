@@ -8,7 +8,7 @@ namespace mf {
 
 // Scheme constants of one sweep axis d (lambda = dt / dx_d).
 template <typename T> struct AxisConst {
-    T lam;        // dt / dx_d            (MUSTA predictor)
+    T lam;        // dt / dx_d            (MUSTA predictor; alpha dt / dx_d as an ablation)
     T half_lam;   // dt / (2 dx_d)        (Hancock half step)
     T half_alam;  // alpha dt / (2 dx_d)  (Lax-Wendroff half step)
     T inv_2alam;  // dx_d / (2 alpha dt)  (Lax-Friedrichs viscosity)

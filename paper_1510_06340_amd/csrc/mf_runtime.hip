@@ -186,10 +186,10 @@ int auto_seg(const AxisGeom& g)
 }
 
 template <typename T>
-void set_axis_const(AxisConst<T>& ac, double dt, double dx, double alpha)
+void set_axis_const(AxisConst<T>& ac, double dt, double dx, double alpha, bool predictor_alpha)
 {
     const double lam = dt / dx;
-    ac.lam = (T)lam;
+    ac.lam = (T)(predictor_alpha ? alpha * lam : lam);
     ac.half_lam = (T)(0.5 * lam);
     ac.half_alam = (T)(0.5 * alpha * lam);
     ac.inv_2alam = (T)(1.0 / (2.0 * alpha * lam));
@@ -225,7 +225,7 @@ SweepArgs<T> make_sweep_args(const Event& ev, int d, int seg, unsigned long long
     a.want_smax = want_smax ? 1 : 0;
     a.axis_f = geo.axis_f;
     a.axis_s = geo.axis_s;
-    set_axis_const(a.ac, dt, ev.d.dx[d], ev.d.alpha);
+    set_axis_const(a.ac, dt, ev.d.dx[d], ev.d.alpha, (ev.d.flags & MF_FLAG_PREDICTOR_ALPHA) != 0);
     a.dt = (T)dt;
     if (ev.jet && d == 2) {
         a.jet_pos[0] = ev.jet_x0[0];
@@ -665,6 +665,7 @@ int check_desc(const mf_grid_desc& d)
     if (d.musta_k < 1 || d.musta_k > 64) return fail(MF_ERR_ARG, "musta_k must be in [1, 64]");
     if (d.rk_order != 2 && d.rk_order != 3) return fail(MF_ERR_ARG, "rk_order must be 2 or 3");
     if (!(d.alpha > 0.0) || !std::isfinite(d.alpha)) return fail(MF_ERR_ARG, "alpha must be finite and > 0");
+    if (d.flags & ~(MF_FLAG_STRICT | MF_FLAG_PREDICTOR_ALPHA)) return fail(MF_ERR_ARG, "unknown flag bits");
     return MF_OK;
 }
 

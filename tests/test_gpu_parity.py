@@ -80,6 +80,20 @@ def test_shock_tube_paper_setting(lim):
     assert st["n_floor"] == sto["n_floor"] and st["n_bad"] == sto["n_bad"]
 
 
+def test_predictor_alpha_ablation_parity():
+    """MF_FLAG_PREDICTOR_ALPHA (alpha dt/dx in the MUSTA predictor) against the oracle's alternative reading."""
+    from paper_1510_06340_amd import mf
+    w = I.shock_workload(ny=4, nz=4, k=4, rk=3)
+    w.extra["predictor_alpha"] = True
+    U = I.initial_state(w)
+    Ug, _ = gpu_run(w, U, flags=mf.MF_FLAG_PREDICTOR_ALPHA)
+    Uo, _ = oracle_run(w, U)
+    assert max_rel_err(Ug, Uo) <= TOL64
+    w.extra["predictor_alpha"] = False
+    Ul, _ = oracle_run(w, U)
+    assert max_rel_err(Ul, Uo) > 1e-4   # the readings differ
+
+
 @pytest.mark.parametrize("bc", [I.BC_OUTFLOW, I.BC_PERIODIC])
 def test_hotspot_parity_ragged_grid(bc):
     """Hot spots on a 67x45x38 grid (ragged against every segment and block shape), MC, k = 3."""

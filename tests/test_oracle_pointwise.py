@@ -283,3 +283,27 @@ def test_musta_linearised_about_rest(ora, k, lam):
         if l < k:
             uL, uR = uL - lam * (Fh - A @ uL), uR - lam * (A @ uR - Fh)
     np.testing.assert_allclose(F - F0, Fh, rtol=0, atol=1e-5 * eps)
+
+
+def test_predictor_coefficient_ablation(ora):
+    """Reading Q2 and its alternative (alpha dt/dx in the MUSTA predictor).
+
+    k = 1 has no predictor step, so both readings give the same flux.  For the
+    linearised problem about rest both readings converge, as k grows, to the
+    same flux, the alternative in fewer stages; that limit has less viscosity
+    than the upwind (Godunov) flux, so neither reading turns MUSTA into an
+    exact Riemann solver."""
+    cs = math.sqrt(1.0 / 3.0)
+    d = 1e-7
+    UL = np.array([1.0 + d, 0.0, 0.0, 0.0]).reshape(4, 1)
+    UR = np.array([1.0, 0.0, 0.0, 0.0]).reshape(4, 1)
+
+    def mass_flux(k, alt, lam=0.3):
+        return float(ora.musta(ora.Problem(k=k, predictor_alpha=alt), 0, lam, UL, UR)[0, 0])
+
+    assert mass_flux(1, False) == mass_flux(1, True)
+    lim_lit, lim_alt = mass_flux(256, False), mass_flux(256, True)
+    assert abs(lim_lit - lim_alt) <= 1e-6 * abs(lim_alt)   # rounding of a flux of O(d)
+    assert abs(mass_flux(8, True) - lim_alt) < 0.1 * abs(mass_flux(8, False) - lim_lit)
+    upwind = 0.5 * cs * d
+    assert 0.7 < lim_alt / upwind < 0.9
