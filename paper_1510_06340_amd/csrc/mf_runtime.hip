@@ -174,12 +174,14 @@ int auto_chunks_x(const AxisGeom& g)
     return (int)std::max<int64_t>(1, std::min<int64_t>(cpw, 64));
 }
 
-// Cells per thread along the sweep axis: enough segments to put about three
-// wavefronts on every SIMD of the 256 compute units, but at least 16 cells
-// per segment (each segment recomputes two reconstructions and one interface).
+// Cells per thread along the sweep axis: enough segments for two rounds of
+// four wavefronts on every SIMD of the 256 compute units (the sweeps run at
+// four wavefronts per SIMD; the second round balances the tail), but at
+// least 16 cells per segment (each segment recomputes two reconstructions
+// and one interface).
 int auto_seg(const AxisGeom& g)
 {
-    const int64_t target_threads = 256LL * 4 * 64 * 3;
+    const int64_t target_threads = 256LL * 4 * 64 * 8;
     int64_t nseg = (target_threads + g.nlines - 1) / g.nlines;
     nseg = std::max<int64_t>(1, std::min<int64_t>(nseg, (g.N + 15) / 16));
     return (int)((g.N + nseg - 1) / nseg);
