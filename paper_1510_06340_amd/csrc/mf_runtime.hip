@@ -165,11 +165,13 @@ AxisGeom axis_geom(const int32_t n[3], int d)
 }
 
 // x sweep (lanes along x): chunks of 64 row items per wavefront, chosen to
-// give about two rounds of three wavefronts on every SIMD.
-int auto_chunks_x(const AxisGeom& g)
+// give about two rounds of three wavefronts on every SIMD.  With the table
+// EoS the cost per cell varies with the local Newton iterations, and smaller
+// work units (about five rounds) balance it better.
+int auto_chunks_x(const AxisGeom& g, bool table)
 {
     const int64_t items = g.nlines * ((int64_t)g.N + 2);
-    const int64_t target_waves = 256LL * 4 * 3 * 2;
+    const int64_t target_waves = 256LL * 4 * 3 * (table ? 5 : 2);
     int64_t cpw = (items + 64 * target_waves - 1) / (64 * target_waves);
     return (int)std::max<int64_t>(1, std::min<int64_t>(cpw, 64));
 }
@@ -178,12 +180,14 @@ int auto_chunks_x(const AxisGeom& g)
 // four wavefronts on every SIMD of the 256 compute units (the sweeps run at
 // four wavefronts per SIMD; the second round balances the tail), but at
 // least 16 cells per segment (each segment recomputes two reconstructions
-// and one interface).
-int auto_seg(const AxisGeom& g)
+// and one interface).  With the table EoS (uneven cost per cell): four
+// rounds and at least 8 cells.
+int auto_seg(const AxisGeom& g, bool table)
 {
-    const int64_t target_threads = 256LL * 4 * 64 * 8;
+    const int64_t target_threads = 256LL * 4 * 64 * (table ? 16 : 8);
+    const int64_t min_cells = table ? 8 : 16;
     int64_t nseg = (target_threads + g.nlines - 1) / g.nlines;
-    nseg = std::max<int64_t>(1, std::min<int64_t>(nseg, (g.N + 15) / 16));
+    nseg = std::max<int64_t>(1, std::min<int64_t>(nseg, (g.N + min_cells - 1) / min_cells));
     return (int)((g.N + nseg - 1) / nseg);
 }
 
@@ -259,10 +263,10 @@ int64_t axis_tiles(const Event& ev, int d, int seg, int block)
     return ((geo.nlines + block - 1) / block) * nseg;
 }
 
-int default_shape(const Event& ev, int d)
+int default_shape(const Event& ev, int d, bool table)
 {
     const AxisGeom geo = axis_geom(ev.d.n, d);
-    return d == 0 ? auto_chunks_x(geo) : auto_seg(geo);
+    return d == 0 ? auto_chunks_x(geo, table) : auto_seg(geo, table);
 }
 
 template <typename T, class Eos>
@@ -271,7 +275,7 @@ int run_stage(mf_grid_s* g, const Eos& eos, Event& ev, unsigned long long* stats
 {
     for (int d = 0; d < 3; d++) {
         const AxisGeom geo = axis_geom(ev.d.n, d);
-        int seg = g->seg_override[d] > 0 ? g->seg_override[d] : default_shape(ev, d);
+        int seg = g->seg_override[d] > 0 ? g->seg_override[d] : default_shape(ev, d, g->eos_kind == MF_EOS_TABLE);
         if (d > 0) seg = std::min(seg, geo.N);
         SweepArgs<T> a = make_sweep_args<T>(ev, d, seg, stats, uin, u0, out, kind, dt, want_smax);
         const bool jet = ev.jet && d == 2;
@@ -467,13 +471,14 @@ int batch_tune(mf_grid_s* g, const Eos& eos, const double* dt)
     for (int e = 0; e < ne; e++) tnow[e] = g->ev[e].t;
     MF_HIP(hipMemcpyAsync(b.t_dev, tnow.data(), sizeof(double) * ne, hipMemcpyHostToDevice, b.stream));
     const int cand_x[4] = {4, 8, 16, 32};
-    const int cand_yz[4] = {16, 32, 64, 128};
+    const int cand_yz[5] = {8, 16, 32, 64, 128};
     const int blocks[2] = {128, 256};
     int best_shape[3] = {0, 0, 0}, best_block[3] = {256, 256, 256};
     for (int d = 0; d < 3; d++) {
         float best = 1e30f;
         for (int bi = 0; bi < 2; bi++) {
-            for (int ci = 0; ci < 4; ci++) {
+            const int ncand = d == 0 ? 4 : 5;
+            for (int ci = 0; ci < ncand; ci++) {
                 int shape[3] = {8, 64, 64}, block[3] = {256, 256, 256};
                 for (int q = 0; q < 3; q++) {
                     shape[q] = best_shape[q] ? best_shape[q] : shape[q];
