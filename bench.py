@@ -30,6 +30,12 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, GB/s
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector (FMA = 2 flops)
 FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector
 
+# HBM bytes per axis-sweep launch (average of x, y, z) of the 256^3 FP64 hot-spot
+# configuration with the default launch shapes, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs scaled by a 1 GiB device copy (FETCH x 2, WRITE x 1); see
+# profiles/k_sweep_hotspot256_fp64.md.  Other configurations report null.
+TRAFFIC_HOTSPOT256_F64 = 1.578e9
+
 # Algorithmic operation counts (add, sub, mul, div, sqrt, min/max each 1 flop).
 C2P_FLUX = 24   # ideal-EoS con2prim + physical flux along one axis
 LIMITER_OPS = {0: 2, 1: 1, 2: 5, 3: 6, 4: 4, 5: 7}
@@ -265,7 +271,9 @@ def main(argv=None):
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / peak,
-            "traffic": None,
+            "traffic": (TRAFFIC_HOTSPOT256_F64 if (args.workload == "hotspot" and w.n == (256, 256, 256)
+                                                    and args.dtype == "f64" and table is None and args.seg is None
+                                                    and args.block == 256) else None),
             "flops_per_cell_axis": fl_axis,
             "avg_launch_ms": avg_launch_ms,
             "launches": n_launch,
