@@ -202,8 +202,8 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU layout is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU (asked for --gpus {args.gpus}); events shard across "
+              "GPUs by event and one large grid by z slabs, which is not built", file=sys.stderr)
         return 2
 
     import torch

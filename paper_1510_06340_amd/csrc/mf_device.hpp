@@ -200,13 +200,13 @@ template <typename T> struct EosIdeal {
 // is replaced by bisection.  FP64 only.
 // ---------------------------------------------------------------------------
 struct EosTable {
-    static constexpr int kWaves = 2;
+    static constexpr int kWaves = 2;  // minimum waves per SIMD the sweeps are compiled for (they get 3-4)
     const double4* rec;  // 2 (n + 1) records: piece k = rec[2k], rec[2k + 1]
     int32_t n;           // nodes
     int32_t log_uniform; // piece from log2(e) (then a fix-up); else bisection
     float lg0;           // log2 e_0
     float inv_dlg;       // (n - 1) / (log2 e_{n-1} - log2 e_0)
-    int32_t max_iter;
+    int32_t max_iter;    // Newton steps at most
     // learned seed: predictions of the MLP on a grid over (ln E, |M|/E),
     // read by bilinear interpolation (the grid is filled by the MLP kernel)
     const float* seed;   // [sg0][sg1] or nullptr (plain solve)

@@ -1,16 +1,18 @@
 // mf_kernels.hip -- gfx950 kernels of the MUSTA-FORCE step.
 //
-// Axis sweep (k_sweep): one thread owns a segment of one grid line along the
-// sweep axis and marches along it with a three-cell register window, so each
-// cell's reconstruction + Hancock half step and each interface's MUSTA-FORCE
-// flux is computed once (plus two cells and one interface of overlap per
-// segment).  Lanes of a wavefront own neighbouring lines: for the y and z
-// sweeps they are neighbouring x cells, so every load and store is one
-// contiguous 512-byte (FP64) row; for the x sweep they are neighbouring rows
-// and each lane's cache line is reused over the following steps of the march.
+// y and z sweeps (k_sweep): one thread owns a segment of one grid line along
+// the sweep axis and marches along it with a three-cell register window, so
+// each cell's reconstruction + Hancock half step and each interface's
+// MUSTA-FORCE flux is computed once (plus two cells and one interface of
+// overlap per segment).  Lanes of a wavefront own neighbouring x cells, so
+// every load and store is one contiguous 512-byte (FP64) row.
+// x sweep (k_sweep_x): lanes lie along x over a stream of row items and pass
+// face states and fluxes to their neighbours by DPP lane shifts.
 // The three sweeps of a Runge-Kutta stage accumulate L = ((Lx + Ly) + Lz) in
 // a library-owned array; the z sweep also adds the source term, applies the
 // Runge-Kutta combine and (last stage) reduces the max characteristic speed.
+// k_batch_sweep runs the same per-thread code for many events from one
+// persistent launch over a tile queue.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
