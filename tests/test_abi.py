@@ -61,8 +61,9 @@ def _init(lib, desc, ptrs=None):
 
 
 @pytest.mark.parametrize("field,value", [
-    ("n", (0, 4, 4)), ("dx", (0.1, 0.0, 0.1)), ("bc", (0, 2, 0)), ("dtype", 7), ("limiter", 9),
-    ("musta_k", 0), ("rk_order", 4), ("alpha", -1.0)])
+    ("n", (0, 4, 4)), ("n", (65536, 65536, 2)), ("dx", (0.1, 0.0, 0.1)), ("dx", (0.1, float("nan"), 0.1)),
+    ("bc", (0, 2, 0)), ("origin", (0.0, float("inf"), 0.0)), ("dtype", 7), ("limiter", 9), ("musta_k", 0),
+    ("musta_k", 65), ("rk_order", 4), ("alpha", -1.0), ("flags", 4)])
 def test_invalid_descriptors_are_rejected(lib, field, value):
     d = mf.make_desc((4, 4, 4), (0.1, 0.1, 0.1), (0, 0, 0), (0, 0, 0))
     if isinstance(value, tuple):
@@ -72,6 +73,14 @@ def test_invalid_descriptors_are_rejected(lib, field, value):
     rc, h = _init(lib, d)
     assert rc == mf.MF_ERR_ARG and not h.value
     assert len(mf.last_error()) > 0
+
+
+def test_no_events_is_rejected(lib):
+    d = mf.make_desc((4, 4, 4), (0.1, 0.1, 0.1), (0, 0, 0), (0, 0, 0))
+    h = C.c_void_p()
+    arr = (C.c_void_p * 4)(1, 2, 3, 4)
+    assert lib.mf_grid_init(C.byref(h), C.byref(d), 0, arr, None) == mf.MF_ERR_ARG
+    assert not h.value and "n_events" in mf.last_error()
 
 
 def test_null_arguments_are_rejected(lib):
