@@ -1074,7 +1074,7 @@ int64_t mf_mlp_workspace(int64_t n) { return n > 0 ? mlp_grad_partials(n) * (MF_
 
 int mf_mlp_forward(const float* params, const float* X, int64_t n, float* y, void* stream)
 {
-    if (!params || !X || !y || n < 0) return fail(MF_ERR_ARG, "bad argument");
+    if (!params || n < 0 || (n > 0 && (!X || !y))) return fail(MF_ERR_ARG, "bad argument");
     hipError_t e = mlp_forward(params, X, n, y, (hipStream_t)stream);
     if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("mlp forward: ") + hipGetErrorString(e));
     return MF_OK;

@@ -130,6 +130,29 @@ def test_every_limiter_stage_count_and_rk(lim):
             assert st["n_floor"] == sto["n_floor"] and st["n_bad"] == sto["n_bad"]
 
 
+def test_zero_steps_and_empty_calls():
+    """nsteps = 0 leaves the state untouched; zero-length con2prim and network calls are no-ops."""
+    import torch
+    from paper_1510_06340_amd import mf
+    w = I.shock_workload(nx=20, ny=3, nz=2)
+    U = I.initial_state(w)
+    Ug, st = gpu_run(w, U, nsteps=0)
+    assert np.array_equal(Ug, U) and st["steps"] == 0 and st["t"] == 0.0
+    dev = to_dev(U)
+    g = mf.Grid([mf.desc_from_workload(w)], [dev])
+    try:
+        g.set_eos_ideal(w.cs2)
+        empty = [torch.empty(0, dtype=torch.float64, device="cuda") for _ in range(5)]
+        g.con2prim(empty[:4], empty)
+        sts = g.batch_step([w.dt], 0)
+        assert sts[0]["steps"] == 0
+    finally:
+        g.free()
+    params = torch.zeros(mf.MF_MLP_PARAMS, device="cuda")
+    mf.mlp_forward(params, torch.empty((0, 2), device="cuda"), torch.empty(0, device="cuda"))
+    torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("n", [(1, 1, 1), (2, 1, 1), (1, 5, 1), (1, 1, 7), (3, 1, 130), (130, 2, 3), (65, 66, 1)])
 def test_degenerate_and_thin_grids(n):
     rng = np.random.default_rng(sum(n))
