@@ -42,7 +42,7 @@ class Params(C.Structure):
         ("eos", C.c_int32), ("cs2", C.c_double), ("ntab", C.c_int32),
         ("etab", C.POINTER(C.c_double)), ("ptab", C.POINTER(C.c_double)), ("mtab", C.POINTER(C.c_double)),
         ("jet", C.c_int32), ("jet_x0", C.c_double * 3), ("jet_v", C.c_double), ("jet_dedx", C.c_double),
-        ("jet_sigma", C.c_double), ("predictor_alpha", C.c_int32),
+        ("jet_sigma", C.c_double), ("predictor_alpha", C.c_int32), ("unsplit_hancock", C.c_int32),
     ]
 
 
@@ -98,7 +98,7 @@ class Problem:
 
     def __init__(self, n=(1, 1, 1), dx=(1.0, 1.0, 1.0), xlo=(0.0, 0.0, 0.0), bc=(0, 0, 0),
                  limiter=LIM_MINMOD, k=2, rk=2, alpha=3.0, cs2=1.0 / 3.0, table=None, jet=None,
-                 predictor_alpha=False):
+                 predictor_alpha=False, unsplit_hancock=False):
         self.p = Params()
         self.p.n[:] = [int(v) for v in n]
         self.p.bc[:] = [int(v) for v in bc]
@@ -116,6 +116,7 @@ class Problem:
             self.p.ntab = len(e)
             self.p.etab, self.p.ptab, self.p.mtab = _p(e), _p(p), _p(m)
         self.p.predictor_alpha = 1 if predictor_alpha else 0
+        self.p.unsplit_hancock = 1 if unsplit_hancock else 0
         self.p.jet = 0
         if jet is not None:
             self.p.jet = 1
@@ -129,7 +130,8 @@ class Problem:
             jet = dict(x0=jet_x0, v=w.jet["v"], dedx=w.jet["dedx"], sigma=w.jet["sigma"])
         return cls(n=w.n, dx=w.dx, xlo=w.xlo, bc=w.bc, limiter=w.limiter, k=w.k, rk=w.rk,
                    alpha=w.alpha, cs2=w.cs2, table=table, jet=jet,
-                   predictor_alpha=w.extra.get("predictor_alpha", False))
+                   predictor_alpha=w.extra.get("predictor_alpha", False),
+                   unsplit_hancock=w.extra.get("unsplit_hancock", False))
 
     @property
     def ref(self):

@@ -68,6 +68,9 @@ typedef struct {
     double jet_sigma;   /* Gaussian width of the deposition */
     int32_t predictor_alpha; /* 1: alpha dt/dx in the MUSTA predictor (the alternative
                                 reading of Sec. 2.4; 0: dt/dx as printed) */
+    int32_t unsplit_hancock; /* 1: one Hancock correction per cell from all three axes,
+                                added to all six faces (the alternative reading of the
+                                multi-dimensional MUSCL-Hancock step, Sec. 2.4); 0: per axis */
 } ora_params;
 
 typedef struct {
@@ -369,10 +372,11 @@ void ora_musta(const ora_params* P, int32_t d, double lam, int64_t n, const doub
 /* ---------------------------------------------------------------------- */
 
 /* u: N+4 padded cells (u[j] is cell j-2).  Adds -(F_{i+1/2} - F_{i-1/2})/dx
- * into out[i], i = 0..N-1. */
+ * into out[i], i = 0..N-1.  dl: Hancock corrections of cells -1..N (dl[j] is
+ * cell j-1) from the unsplit step, or NULL for the per-axis step. */
 static void line_rhs(const ora_params* P, int d, int N, double lam, double dxd,
                      double (*u)[4], double (*uLt)[4], double (*uRt)[4], double (*F)[4],
-                     double (*out)[4], ora_counters* cnt)
+                     double (*out)[4], const double (*dl)[4], ora_counters* cnt)
 {
     /* MUSCL reconstruction and Hancock half step for cells -1..N */
     for (int i = -1; i <= N; i++) {
@@ -386,6 +390,13 @@ static void line_rhs(const ora_params* P, int d, int N, double lam, double dxd,
             double D = limiter(P->limiter, a, b);
             UL[c] = u0[c] - 0.5 * D;
             UR[c] = u0[c] + 0.5 * D;
+        }
+        if (dl) {
+            for (int c = 0; c < 4; c++) {
+                uLt[i + 1][c] = UL[c] + dl[i + 1][c];
+                uRt[i + 1][c] = UR[c] + dl[i + 1][c];
+            }
+            continue;
         }
         flux(P, d, UL, FLc, cnt);
         flux(P, d, UR, FRc, cnt);
@@ -408,6 +419,51 @@ static int64_t ghost_index(int j, int N, int bc)
     return j < 0 ? 0 : N - 1;
 }
 
+/* Unsplit Hancock corrections on the grid extended by one ghost cell per
+ * side, (nx+2)(ny+2)(nz+2) cells, cell (i,j,k) at ((k+1)(ny+2) + j+1)(nx+2) + i+1:
+ *   delta = sum_d (dt / (2 dx_d)) (F_d(U^{L,d}) - F_d(U^{R,d})),
+ * with U^{L,d}, U^{R,d} = U -/+ phi_d / 2 the limited faces along each axis,
+ * and the state outside the grid from the boundary conditions per axis. */
+static double* unsplit_corrections(const ora_params* P, const double* U, double dt, ora_counters* cnt_out)
+{
+    const int nx = P->n[0], ny = P->n[1], nz = P->n[2];
+    const int64_t ncell = (int64_t)nx * ny * nz;
+    const int ex = nx + 2, ey = ny + 2, ez = nz + 2;
+    const int64_t next = (int64_t)ex * ey * ez;
+    double* dl = malloc(sizeof(double) * 4 * (size_t)next);
+    int64_t nf = 0, nb = 0, ni = 0, nc = 0;
+#pragma omp parallel for schedule(static) reduction(+ : nf, nb, ni, nc)
+    for (int64_t e = 0; e < next; e++) {
+        const int i = (int)(e % ex) - 1, j = (int)((e / ex) % ey) - 1, k = (int)(e / ((int64_t)ex * ey)) - 1;
+        ora_counters cnt = {0, 0, 0, 0};
+        double delta[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int d = 0; d < 3; d++) {
+            double w[3][4];  /* cells -1, 0, +1 along d */
+            for (int s = -1; s <= 1; s++) {
+                int q[3] = {i, j, k};
+                q[d] += s;
+                const int64_t idx = ghost_index(q[0], nx, P->bc[0]) +
+                                    nx * (ghost_index(q[1], ny, P->bc[1]) + ny * ghost_index(q[2], nz, P->bc[2]));
+                for (int c = 0; c < 4; c++) w[s + 1][c] = U[c * ncell + idx];
+            }
+            double UL[4], UR[4], FL[4], FR[4];
+            for (int c = 0; c < 4; c++) {
+                const double D = limiter(P->limiter, w[1][c] - w[0][c], w[2][c] - w[1][c]);
+                UL[c] = w[1][c] - 0.5 * D;
+                UR[c] = w[1][c] + 0.5 * D;
+            }
+            flux(P, d, UL, FL, &cnt);
+            flux(P, d, UR, FR, &cnt);
+            const double lam = dt / P->dx[d];
+            for (int c = 0; c < 4; c++) delta[c] = delta[c] + 0.5 * lam * (FL[c] - FR[c]);
+        }
+        for (int c = 0; c < 4; c++) dl[4 * e + c] = delta[c];
+        nf += cnt.n_floor; nb += cnt.n_bad; ni += cnt.n_iter; nc += cnt.n_calls;
+    }
+    cnt_out->n_floor += nf; cnt_out->n_bad += nb; cnt_out->n_iter += ni; cnt_out->n_calls += nc;
+    return dl;
+}
+
 /* L(U, t) = -(dF/dx + dG/dy + dH/dz) + S, summed as ((Lx + Ly) + Lz) + S. */
 static void rhs(const ora_params* P, const double* U, double t, double dt, double* L,
                 ora_counters* cnt_out)
@@ -417,6 +473,9 @@ static void rhs(const ora_params* P, const double* U, double t, double dt, doubl
     const int64_t stride[3] = {1, nx, (int64_t)nx * ny};
     memset(L, 0, sizeof(double) * 4 * (size_t)ncell);
     int64_t nf = 0, nb = 0, ni = 0, nc = 0;
+    ora_counters cpre = {0, 0, 0, 0};
+    double* dl3 = P->unsplit_hancock ? unsplit_corrections(P, U, dt, &cpre) : NULL;
+    const int64_t estride[3] = {1, nx + 2, (int64_t)(nx + 2) * (ny + 2)};
     for (int d = 0; d < 3; d++) {
         const int N = P->n[d];
         const double lam = dt / P->dx[d];
@@ -430,6 +489,7 @@ static void rhs(const ora_params* P, const double* U, double t, double dt, doubl
             double(*uRt)[4] = malloc(sizeof(double[4]) * (size_t)(N + 2));
             double(*F)[4] = malloc(sizeof(double[4]) * (size_t)(N + 1));
             double(*out)[4] = malloc(sizeof(double[4]) * (size_t)N);
+            double(*dl)[4] = dl3 ? malloc(sizeof(double[4]) * (size_t)(N + 2)) : NULL;
             ora_counters cnt = {0, 0, 0, 0};
 #pragma omp for schedule(static)
             for (int64_t line = 0; line < nlines; line++) {
@@ -440,14 +500,19 @@ static void rhs(const ora_params* P, const double* U, double t, double dt, doubl
                     int64_t idx = base + ghost_index(j, N, P->bc[d]) * stride[d];
                     for (int c = 0; c < 4; c++) u[j + 2][c] = U[c * ncell + idx];
                 }
-                line_rhs(P, d, N, lam, P->dx[d], u, uLt, uRt, F, out, &cnt);
+                if (dl) {  /* corrections of cells -1..N along the line */
+                    const int64_t ebase = (i1 + 1) * estride[a1] + (i2 + 1) * estride[a2];
+                    for (int j = -1; j <= N; j++)
+                        for (int c = 0; c < 4; c++) dl[j + 1][c] = dl3[4 * (ebase + (int64_t)(j + 1) * estride[d]) + c];
+                }
+                line_rhs(P, d, N, lam, P->dx[d], u, uLt, uRt, F, out, (const double(*)[4])dl, &cnt);
                 for (int j = 0; j < N; j++) {
                     int64_t idx = base + (int64_t)j * stride[d];
                     for (int c = 0; c < 4; c++) L[c * ncell + idx] = L[c * ncell + idx] + out[j][c];
                 }
             }
             nf += cnt.n_floor; nb += cnt.n_bad; ni += cnt.n_iter; nc += cnt.n_calls;
-            free(u); free(uLt); free(uRt); free(F); free(out);
+            free(u); free(uLt); free(uRt); free(F); free(out); free(dl);
         }
     }
     if (P->jet) {
@@ -468,6 +533,8 @@ static void rhs(const ora_params* P, const double* U, double t, double dt, doubl
             L[ncell + idx] = L[ncell + idx] + P->jet_v * SE;
         }
     }
+    free(dl3);
+    nf += cpre.n_floor; nb += cpre.n_bad; ni += cpre.n_iter; nc += cpre.n_calls;
     cnt_out->n_floor += nf; cnt_out->n_bad += nb; cnt_out->n_iter += ni; cnt_out->n_calls += nc;
 }
 

@@ -51,3 +51,37 @@ def test_hubble_initial_state_is_the_exact_solution():
     Mabs = np.sqrt((U[1:] ** 2).sum(0))[inside]
     np.testing.assert_allclose(Mabs, (4.0 / 3.0) * e * g2 * v, rtol=1e-14, atol=1e-14)
     assert np.all(U[:, ~inside] == 0.0)
+
+
+def test_unsplit_hancock_ablation(ora):
+    """Reading Q4 and its alternative: one Hancock correction per cell from all three axes,
+    added to all six faces.
+
+    A planar problem cannot tell them apart: the transverse slopes vanish and equal
+    corrections on both faces of every transverse interface cancel, so the shock tube
+    is bitwise the same.  In 3-D the alternative still converges at first order on
+    the Hubble-like expansion, with a larger error than the per-axis step."""
+    w = I.shock_workload(ny=3, nz=2, k=3, rk=2, steps=15)
+    U = I.initial_state(w)
+    A, _ = ora.step(ora.Problem.from_workload(w), U, w.dt, w.steps)
+    w.extra["unsplit_hancock"] = True
+    B, _ = ora.step(ora.Problem.from_workload(w), U, w.dt, w.steps)
+    assert np.array_equal(A, B)
+
+    def unsplit_errors(n, dx, dt, steps):
+        w = I.hubble_workload(n=n, dx=dx, dt=dt, steps=steps)
+        w.extra["unsplit_hancock"] = True
+        U = I.initial_state(w)
+        prob = ora.Problem.from_workload(w)
+        V, _ = ora.step(prob, U, w.dt, w.steps, 2.0)
+        prim, _ = ora.con2prim(prob, V)
+        xs = I.cell_centres(n, dx, w.xlo[0])
+        r = np.sqrt(xs[:, None, None] ** 2 + xs[None, :, None] ** 2 + xs[None, None, :] ** 2)
+        sel = r < 0.6
+        ee, _ = hubble.exact(r[sel], 2.0 + steps * dt)
+        return float((np.abs(prim[0][sel] - ee) / ee).max())
+
+    u1, u2 = unsplit_errors(32, 0.1, 0.03, 10), unsplit_errors(64, 0.05, 0.015, 20)
+    s1, _, _ = central_errors(ora, 32, 0.1, 0.03, 10)
+    print(f"\ncentral e error, unsplit Hancock: {u1:.2e} -> {u2:.2e} (per-axis at 32^3: {s1:.2e})")
+    assert u1 / u2 > 1.8 and u1 > 1.2 * s1
