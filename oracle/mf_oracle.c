@@ -31,6 +31,14 @@
  *  - Unphysical states: E <= 0 or non-finite -> counted, zero flux;
  *    |M| > (1 - 1e-12) E -> M scaled to that bound for the evaluation only,
  *    counted.
+ * Two options give the alternative readings for ablations: predictor_alpha
+ * (alpha*dt/dx in the MUSTA predictor) and unsplit_hancock (one Hancock
+ * correction per cell from all three axes, added to all six faces).
+ *
+ * Parity unpinned: the paper prints no values that fix these readings (or
+ * the combination of them); they are pinned only through invariants
+ * (uniform states, mirror and planar symmetry, conservation) and exact
+ * solutions (the shock tube and the Hubble-like expansion).
  */
 #include <math.h>
 #include <stdint.h>

@@ -307,3 +307,18 @@ def test_predictor_coefficient_ablation(ora):
     assert abs(mass_flux(8, True) - lim_alt) < 0.1 * abs(mass_flux(8, False) - lim_lit)
     upwind = 0.5 * cs * d
     assert 0.7 < lim_alt / upwind < 0.9
+
+
+def test_totals_are_compensated_sums(ora):
+    """sum(U) dV by compensated summation: equal to the exactly rounded sum (math.fsum)
+    even for terms of wildly mixed magnitude and sign, where naive summation fails."""
+    rng = np.random.default_rng(11)
+    n = (17, 9, 5)
+    U = rng.normal(size=(4,) + n[::-1]) * np.exp(rng.uniform(-30, 30, size=(4,) + n[::-1]))
+    U[0, 0, 0, 0], U[0, 1, 0, 0] = 1e300, -1e300   # exact cancellation of the two largest terms
+    dx = (0.1, 0.2, 0.3)
+    T = ora.totals(ora.Problem(n=n, dx=dx), U)
+    dV = dx[0] * dx[1] * dx[2]
+    for c in range(4):
+        exact = math.fsum(U[c].ravel().tolist()) * dV
+        assert abs(T[c] - exact) <= 4e-16 * abs(exact), (c, T[c], exact)
