@@ -214,25 +214,36 @@ struct EosTable {
     float seed_lnE0, seed_inv_dlnE;  // grid origin and inverse spacing in ln E
     int32_t seed_output;             // 0: grid holds ln e; 1: the bracket fraction (E - e) E / |M|^2
 
-    // The piece of e (e >= 0): (lo, hi, x, w) in a, (y, c1, c2, c3) in b.
-    __device__ __forceinline__ void piece(double e, double4& a, double4& b) const
+    // Cubic of one piece at e: p and dp/de.
+    __device__ __forceinline__ static void cubic(double e, const double4& a, const double4& b, double& p,
+                                                 double& dp)
     {
-        int k;
+        const double t = (e - a.z) * a.w;
+        p = fma(t, fma(t, fma(t, b.w, b.z), b.y), b.x);
+        dp = a.w * fma(t, fma(t, 3.0 * b.w, 2.0 * b.z), b.y);
+    }
+
+    // p(e) and dp/de (e >= 0).  On log-uniform nodes the piece comes from a
+    // single-precision log2, which can be one piece off next to a node: the
+    // cubic of the first guess is evaluated at once (so the piece's loads are
+    // issued together), and lanes outside that piece's bounds redo it with the
+    // right piece inside a wave-uniform branch.
+    __device__ __forceinline__ void eval(double e, double& p, double& dp) const
+    {
         if (log_uniform) {
             float u = (__builtin_amdgcn_logf((float)e) - lg0) * inv_dlg;  // log2 (about 1 ulp)
             u = fminf(fmaxf(u, -1.0f), (float)n);                          // also maps NaN to -1
-            k = (int)floorf(u) + 1;
+            int k = (int)floorf(u) + 1;
             k = k < 0 ? 0 : (k > n ? n : k);
-            a = rec[2 * k];
-            b = rec[2 * k + 1];
-            // the single-precision log can put e one piece off near a node
+            const double4 a = rec[2 * k];
+            const double4 b = rec[2 * k + 1];
+            cubic(e, a, b, p, dp);
             const bool off = (e < a.x) | (e >= a.y);
             if (__any(off)) {
                 if (off) {
                     while (k > 0 && e < rec[2 * k].x) k--;
                     while (k < n && e >= rec[2 * k].y) k++;
-                    a = rec[2 * k];
-                    b = rec[2 * k + 1];
+                    cubic(e, rec[2 * k], rec[2 * k + 1], p, dp);
                 }
             }
         } else {
@@ -242,19 +253,8 @@ struct EosTable {
                 if (rec[2 * mid].x <= e) lo = mid;
                 else hi = mid;
             }
-            k = lo;
-            a = rec[2 * k];
-            b = rec[2 * k + 1];
+            cubic(e, rec[2 * lo], rec[2 * lo + 1], p, dp);
         }
-    }
-
-    __device__ __forceinline__ void eval(double e, double& p, double& dp) const
-    {
-        double4 a, b;
-        piece(e, a, b);
-        const double t = (e - a.z) * a.w;
-        p = fma(t, fma(t, fma(t, b.w, b.z), b.y), b.x);
-        dp = a.w * fma(t, fma(t, 3.0 * b.w, 2.0 * b.z), b.y);
     }
 
     // Root e of g on the bracket [lo, E], starting from e_start (inside the
