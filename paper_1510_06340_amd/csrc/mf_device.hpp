@@ -204,7 +204,8 @@ struct EosTable {
     const double4* rec;  // 2 (n + 1) records: piece k = rec[2k], rec[2k + 1]
     int32_t n;           // nodes
     int32_t log_uniform; // piece from log2(e) (then a fix-up); else bisection
-    float lg0;           // log2 e_0
+    float lg0;           // log2 e_0 - (log2 e_{n-1} - log2 e_0) / (n - 1): piece k covers [k, k + 1) in
+                         // u = (log2 e - lg0) * inv_dlg
     float inv_dlg;       // (n - 1) / (log2 e_{n-1} - log2 e_0)
     int32_t max_iter;    // Newton steps at most
     // learned seed: predictions of the MLP on a grid over (ln E, |M|/E),
@@ -213,6 +214,12 @@ struct EosTable {
     int32_t sg0, sg1;
     float seed_lnE0, seed_inv_dlnE;  // grid origin and inverse spacing in ln E
     int32_t seed_output;             // 0: grid holds ln e; 1: the bracket fraction (E - e) E / |M|^2
+
+    // Piece k: records 2k and 2k + 1 (the table is far below 4 GiB, so a 32-bit byte offset).
+    __device__ __forceinline__ const double4* piece_ptr(int k) const
+    {
+        return reinterpret_cast<const double4*>(reinterpret_cast<const char*>(rec) + (uint32_t)k * 64u);
+    }
 
     // Cubic of one piece at e: p and dp/de.
     __device__ __forceinline__ static void cubic(double e, const double4& a, const double4& b, double& p,
@@ -232,18 +239,18 @@ struct EosTable {
     {
         if (log_uniform) {
             float u = (__builtin_amdgcn_logf((float)e) - lg0) * inv_dlg;  // log2 (about 1 ulp)
-            u = fminf(fmaxf(u, -1.0f), (float)n);                          // also maps NaN to -1
-            int k = (int)floorf(u) + 1;
-            k = k < 0 ? 0 : (k > n ? n : k);
-            const double4 a = rec[2 * k];
-            const double4 b = rec[2 * k + 1];
+            u = fminf(fmaxf(u, 0.0f), (float)n + 0.5f);                    // also maps NaN to 0
+            int k = (int)u;                                                // in [0, n]
+            const double4* r = piece_ptr(k);
+            const double4 a = r[0];
+            const double4 b = r[1];
             cubic(e, a, b, p, dp);
             const bool off = (e < a.x) | (e >= a.y);
             if (__any(off)) {
                 if (off) {
-                    while (k > 0 && e < rec[2 * k].x) k--;
-                    while (k < n && e >= rec[2 * k].y) k++;
-                    cubic(e, rec[2 * k], rec[2 * k + 1], p, dp);
+                    while (k > 0 && e < piece_ptr(k)[0].x) k--;
+                    while (k < n && e >= piece_ptr(k)[0].y) k++;
+                    cubic(e, piece_ptr(k)[0], piece_ptr(k)[1], p, dp);
                 }
             }
         } else {
@@ -253,7 +260,7 @@ struct EosTable {
                 if (rec[2 * mid].x <= e) lo = mid;
                 else hi = mid;
             }
-            cubic(e, rec[2 * lo], rec[2 * lo + 1], p, dp);
+            cubic(e, piece_ptr(lo)[0], piece_ptr(lo)[1], p, dp);
         }
     }
 

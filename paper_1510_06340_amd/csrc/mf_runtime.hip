@@ -799,7 +799,7 @@ int mf_set_eos(mf_grid_t g, int32_t kind, double cs2, const double* e_tab, const
     t.rec = (const double4*)g->table_dev;
     t.n = n_tab;
     t.log_uniform = log_uniform ? 1 : 0;
-    t.lg0 = (float)l0;
+    t.lg0 = (float)(l0 - dl);  // piece k + 1 starts at node k
     t.inv_dlg = (float)(1.0 / dl);
     t.max_iter = 100;
     t.seed = nullptr;
