@@ -214,6 +214,7 @@ struct EosTable {
     int32_t sg0, sg1;
     float seed_lnE0, seed_inv_dlnE;  // grid origin and inverse spacing in ln E
     int32_t seed_output;             // 0: grid holds ln e; 1: the bracket fraction (E - e) E / |M|^2
+    static constexpr double kSeedMinM2 = 1e-3;  // ln e seed only where (|M|/E)^2 > this
 
     // Piece k: records 2k and 2k + 1 (the table is far below 4 GiB, so a 32-bit byte offset).
     __device__ __forceinline__ const double4* piece_ptr(int k) const
@@ -341,7 +342,17 @@ struct EosTable {
             const double q = M2 * Math<double>::rcp(E);
             lo = E - q;
             e_start = 0.5 * (lo + E);
-            if (seed && M2 != 0.0) e_start = seeded_start(E, lo, seed_guess(E, M2, q), cnt);
+            // a guess of ln e carries an error of about 1e-3 relative: where the bracket
+            // (width m^2 E) is narrower than that, its midpoint is the better start, so
+            // that seed is consulted only for m^2 > kSeedMinM2 (wavefronts without such a
+            // state skip the lookup).  A guess of the bracket fraction is scaled by the
+            // bracket and consulted wherever |M| > 0.
+            if (seed) {
+                const bool wide = q > (seed_output == 1 ? 0.0 : kSeedMinM2 * E);
+                if (__any(wide)) {
+                    if (wide) e_start = seeded_start(E, lo, seed_guess(E, M2, q), cnt);
+                }
+            }
         }
         return solve(E, M2, lo, e_start, p, dp, cnt);
     }
