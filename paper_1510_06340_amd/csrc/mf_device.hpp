@@ -534,23 +534,21 @@ __device__ __forceinline__ void musta(T UL[4], T UR[4], int k, const AxisConst<T
 
 // Largest |characteristic speed| of a primitive state over the three axes:
 // lambda_pm = [v_d (1 - cs2) +- cs sqrt((1 - v^2)(1 - v_d^2 - (v^2 - v_d^2) cs2))] / (1 - v^2 cs2).
+// Along axis d the larger magnitude has the sign of v_d and equals
+// (|v_d| B + sqrt(cs2 (1 - v^2)(A - v_d^2 B))) / A with A = 1 - v^2 cs2 and
+// B = 1 - cs2; it increases with |v_d| (its derivative is positive for
+// v_d^2 < 1), so the maximum over the axes is taken on the axis of largest
+// |v_d| and one square root suffices.
 template <typename T>
 __device__ __forceinline__ T max_speed(const T v[3], T cs2)
 {
     const T v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-    const T cs = Math<T>::sqrt(cs2);
-    const T inv = Math<T>::rcp(T(1) - v2 * cs2);
-    T s = T(0);
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-        const T vd = v[d];
-        T rad = (T(1) - v2) * (T(1) - vd * vd - (v2 - vd * vd) * cs2);
-        rad = rad > T(0) ? rad : T(0);
-        const T root = cs * Math<T>::sqrt0(rad);
-        const T a = vd * (T(1) - cs2);
-        s = fmax(s, fmax(fabs((a + root) * inv), fabs((a - root) * inv)));
-    }
-    return s;
+    const T vm = fmax(fabs(v[0]), fmax(fabs(v[1]), fabs(v[2])));
+    const T A = T(1) - v2 * cs2;
+    const T B = T(1) - cs2;
+    T rad = cs2 * ((T(1) - v2) * (A - vm * vm * B));
+    rad = rad > T(0) ? rad : T(0);
+    return (vm * B + Math<T>::sqrt0(rad)) * Math<T>::rcp(A);
 }
 
 }  // namespace mf
