@@ -195,7 +195,8 @@ template <typename T> struct EosIdeal {
 // con2prim (Sec. 2.6): the fixed point v = |M| / (E + p(E - |M| v)) is the
 // root of g(e) = e - E + |M|^2 / (E + p(e)) on the bracket [E (1 - m^2), E],
 // m = |M| / E (g is increasing there for dp/de < 1).  Safeguarded Newton from
-// the bracket midpoint: stop when the Newton correction |de| <= 1e-12 e;
+// the bracket midpoint: stop when the Newton correction |de| <= 1e-7 e (the
+// accepted iterate is then accurate to about 1e-14, see kNewtonTol);
 // otherwise the bracket shrinks with the sign of g and a step that leaves it
 // is replaced by bisection.  FP64 only.
 // ---------------------------------------------------------------------------
@@ -215,6 +216,13 @@ struct EosTable {
     float seed_lnE0, seed_inv_dlnE;  // grid origin and inverse spacing in ln E
     int32_t seed_output;             // 0: grid holds ln e; 1: the bracket fraction (E - e) E / |M|^2
     static constexpr double kSeedMinM2 = 1e-3;  // ln e seed only where (|M|/E)^2 > this
+    // Newton stops when |de| <= kNewtonTol e and returns e - de.  The error of
+    // that iterate is bounded by (max |g''| / (2 min g')) de^2 with
+    // g' >= 1 - m^2 max p' and |g''| <= m^2 (2 max p'^2 / E + max |p''|): for
+    // p' <= 1/3 and e |p''| <= 0.3 (the crossover table) it is below
+    // 1e-14 e, far inside the 1e-12 the solve promises, one iteration sooner
+    // than a stop at |de| <= 1e-12 e (which needs a confirming step).
+    static constexpr double kNewtonTol = 1e-7;
 
     // Piece k: records 2k and 2k + 1 (the table is far below 4 GiB, so a 32-bit byte offset).
     __device__ __forceinline__ const double4* piece_ptr(int k) const
@@ -270,7 +278,8 @@ struct EosTable {
     // shrinking bracket are replaced by bisection.  At rest (M2 = 0) the root
     // is E and no iteration is counted.  On convergence p(e) is carried to the
     // accepted iterate to first order (the remainder is O(de^2) with
-    // |de| <= 1e-12 e, far below rounding), so the root costs no extra lookup.
+    // |de| <= 1e-7 e, below 1e-14 relative for the crossover table), so the
+    // root costs no extra lookup.
     __device__ __forceinline__ double solve(double E, double M2, double lo, double e_start, double& p, double& dp,
                                             Counts& cnt) const
     {
@@ -286,9 +295,9 @@ struct EosTable {
                     const double de = g * Math<double>::rcp(gp);
                     double en = e - de;
                     cnt.iters++;
-                    // converged: accept the (tiny) Newton correction before any bracket test,
+                    // converged: accept the (small) Newton correction before any bracket test,
                     // which could otherwise reject an iterate sitting on the bracket edge
-                    if (fabs(de) <= 1e-12 * e) {
+                    if (fabs(de) <= kNewtonTol * e) {
                         p = p - dp * de;
                         e = en;
                         break;
@@ -342,11 +351,11 @@ struct EosTable {
             const double q = M2 * Math<double>::rcp(E);
             lo = E - q;
             e_start = 0.5 * (lo + E);
-            // a guess of ln e carries an error of about 1e-3 relative: where the bracket
-            // (width m^2 E) is narrower than that, its midpoint is the better start, so
-            // that seed is consulted only for m^2 > kSeedMinM2 (wavefronts without such a
-            // state skip the lookup).  A guess of the bracket fraction is scaled by the
-            // bracket and consulted wherever |M| > 0.
+            // A guess of ln e carries an error of about 1e-3 relative, which beats the
+            // bracket midpoint (off by about m^2 E / 4) only where m^2 > kSeedMinM2, so
+            // that seed is consulted only there (wavefronts without such a state skip
+            // the lookup).  A guess of the bracket fraction is scaled by the bracket and
+            // consulted wherever |M| > 0.
             if (seed) {
                 const bool wide = q > (seed_output == 1 ? 0.0 : kSeedMinM2 * E);
                 if (__any(wide)) {
