@@ -196,7 +196,8 @@ template <typename T> struct EosIdeal {
 // root of g(e) = e - E + |M|^2 / (E + p(e)) on the bracket [E (1 - m^2), E],
 // m = |M| / E (g is increasing there for dp/de < 1).  Safeguarded Newton from
 // the bracket midpoint: stop when the Newton correction |de| <= 1e-7 e (the
-// accepted iterate is then accurate to about 1e-14, see kNewtonTol);
+// accepted iterate is then accurate to about 1e-14, see kNewtonTol) or
+// |de| <= 1e-15 E (the rounding level of g);
 // otherwise the bracket shrinks with the sign of g and a step that leaves it
 // is replaced by bisection.  FP64 only.
 // ---------------------------------------------------------------------------
@@ -223,6 +224,10 @@ struct EosTable {
     // 1e-14 e, far inside the 1e-12 the solve promises, one iteration sooner
     // than a stop at |de| <= 1e-12 e (which needs a confirming step).
     static constexpr double kNewtonTol = 1e-7;
+    // g is a difference of O(E) terms, known to a few ulp of E: a correction
+    // below kNewtonAbsTol E is rounding noise (for |M| -> E the root e << E is
+    // only defined to that absolute level), and the iterate is accepted.
+    static constexpr double kNewtonAbsTol = 1e-15;
 
     // Piece k: records 2k and 2k + 1 (the table is far below 4 GiB, so a 32-bit byte offset).
     __device__ __forceinline__ const double4* piece_ptr(int k) const
@@ -274,7 +279,7 @@ struct EosTable {
     }
 
     // Root e of g on the bracket [lo, E], starting from e_start (inside the
-    // bracket), with p and dp/de at the root.  Newton steps that leave the
+    // bracket; E when M2 = 0), with p and dp/de at the root.  Newton steps that leave the
     // shrinking bracket are replaced by bisection.  At rest (M2 = 0) the root
     // is E and no iteration is counted.  On convergence p(e) is carried to the
     // accepted iterate to first order (the remainder is O(de^2) with
@@ -283,7 +288,7 @@ struct EosTable {
     __device__ __forceinline__ double solve(double E, double M2, double lo, double e_start, double& p, double& dp,
                                             Counts& cnt) const
     {
-        double e = M2 == 0.0 ? E : e_start;
+        double e = e_start;  // = E at rest (the bracket [E - M2/E, E] is a point)
         eval(e, p, dp);
         if (__any(M2 != 0.0)) {  // wavefronts entirely at rest are done
             if (M2 != 0.0) {
@@ -297,7 +302,7 @@ struct EosTable {
                     cnt.iters++;
                     // converged: accept the (small) Newton correction before any bracket test,
                     // which could otherwise reject an iterate sitting on the bracket edge
-                    if (fabs(de) <= kNewtonTol * e) {
+                    if (fabs(de) <= fmax(kNewtonTol * e, kNewtonAbsTol * E)) {
                         p = p - dp * de;
                         e = en;
                         break;
@@ -418,10 +423,8 @@ struct EosTable {
         F[1] = Mx * vD;
         F[2] = My * vD;
         F[3] = Mz * vD;
-        F[1 + D] = F[1 + D] + p;
-        if (!live) {
-            F[0] = 0.0; F[1] = 0.0; F[2] = 0.0; F[3] = 0.0;
-        }
+        // a replaced state is at rest (M = 0, so vD = 0): only the pressure term is non-zero
+        F[1 + D] = live ? F[1 + D] + p : 0.0;
     }
 
     __device__ __forceinline__ void prim(const double u[4], double& e, double& p, double v[3], double& cs2,
