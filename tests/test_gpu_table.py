@@ -54,6 +54,32 @@ def test_table_con2prim_matches_oracle():
     assert 2.0 < iters[3:].mean() < 12.0
 
 
+def test_piece_lookup_at_every_node():
+    """States at rest exactly on every table node and one ulp either side of it (where the
+    single-precision piece index is most often one piece off and the bounds check moves
+    it), plus states below and above the table: p(E) must equal the oracle's interpolant."""
+    import torch
+    from paper_1510_06340_amd import mf
+    e_nodes = np.asarray(TABLE[0])
+    E = np.concatenate([e_nodes, np.nextafter(e_nodes, 0.0), np.nextafter(e_nodes, np.inf),
+                        [1e-6, 5e-4, 2e3, 1e5]])
+    n = E.size
+    U = np.zeros((4, 1, 1, n))
+    U[0, 0, 0] = E
+    prim_o, _ = oracle.con2prim(oracle.Problem(table=TABLE), U)
+    dev = to_dev(U)
+    out = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(5)]
+    g = mf.Grid([mf.make_desc((n, 1, 1), (1, 1, 1), (0, 0, 0), (0, 0, 0))], [dev])
+    g.set_eos_table(*TABLE)
+    g.con2prim(dev, out)
+    torch.cuda.synchronize()
+    pg = out[1].cpu().numpy()
+    g.free()
+    po = prim_o.reshape(5, -1)[1]
+    assert np.array_equal(out[0].cpu().numpy(), E)          # at rest: e = E exactly
+    np.testing.assert_allclose(pg, po, rtol=1e-14, atol=0)
+
+
 def test_crossover_hotspots_parity_small():
     w = I.crossover_workloads(n_events=1, n=40, steps=6)[0]
     w.n = (40, 37, 35)
