@@ -56,6 +56,17 @@ template <> struct Math<float> {
     static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 };
 
+// Wavefront votes.  The ballot of one compare stays a lane mask in scalar
+// registers; the ballot of a combined condition (a & b) is first copied
+// through a vector register (two more vector instructions), so a guard made
+// of several compares takes one ballot per compare and ORs the masks.
+__device__ __forceinline__ uint64_t lanes_where(bool c) { return __builtin_amdgcn_ballot_w64(c); }
+__device__ __forceinline__ bool lane_in(uint64_t mask)
+{
+    const unsigned lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    return (mask >> lane) & 1u;
+}
+
 template <typename T> __device__ __forceinline__ T big_value();
 template <> __device__ __forceinline__ double big_value<double>() { return 1.79769313486231570e308; }
 template <> __device__ __forceinline__ float big_value<float>() { return 3.40282347e38f; }
@@ -150,10 +161,11 @@ template <typename T> struct EosIdeal {
         const T E = u[0], Mx = u[1], My = u[2], Mz = u[3];
         const T M2 = Mx * Mx + My * My + Mz * Mz;
         const T Mlim = mmax<T>() * E;
-        const bool ok = (E > T(0)) & (E <= big_value<T>()) & (M2 <= Mlim * Mlim);
+        const uint64_t bad = lanes_where(!(E > T(0))) | lanes_where(!(E <= big_value<T>())) |
+                             lanes_where(!(M2 <= Mlim * Mlim));
         flux_core<D>(E, Mx, My, Mz, M2, F);
-        if (__any(!ok)) {
-            if (!ok) {
+        if (bad != 0) {
+            if (lane_in(bad)) {
                 T Ef = E, mx = Mx, my = My, mz = Mz, m2 = M2;
                 if (fixup(Ef, mx, my, mz, m2, cnt)) {
                     flux_core<D>(Ef, mx, my, mz, m2, F);
@@ -259,9 +271,9 @@ struct EosTable {
             const double4 a = r[0];
             const double4 b = r[1];
             cubic(e, a, b, p, dp);
-            const bool off = (e < a.x) | (e >= a.y);
-            if (__any(off)) {
-                if (off) {
+            const uint64_t off = lanes_where(e < a.x) | lanes_where(e >= a.y);
+            if (off != 0) {
+                if (lane_in(off)) {
                     while (k > 0 && e < piece_ptr(k)[0].x) k--;
                     while (k < n && e >= piece_ptr(k)[0].y) k++;
                     cubic(e, piece_ptr(k)[0], piece_ptr(k)[1], p, dp);
@@ -395,10 +407,11 @@ struct EosTable {
                                           Counts& cnt) const
     {
         const double Mlim = mmax<double>() * E;
-        const bool ok = (E > 0.0) & (E <= big_value<double>()) & (M2 <= Mlim * Mlim);
+        const uint64_t bad = lanes_where(!(E > 0.0)) | lanes_where(!(E <= big_value<double>())) |
+                             lanes_where(!(M2 <= Mlim * Mlim));
         bool live = true;
-        if (__any(!ok)) {
-            if (!ok) {
+        if (bad != 0) {
+            if (lane_in(bad)) {
                 live = fixup(E, Mx, My, Mz, M2, cnt);
                 if (!live) {
                     E = 1.0; Mx = 0.0; My = 0.0; Mz = 0.0; M2 = 0.0;
