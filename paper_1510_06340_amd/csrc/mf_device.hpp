@@ -83,6 +83,8 @@ struct Counts {
     uint32_t bad = 0;     // E <= 0 or non-finite
     uint32_t iters = 0;   // root-finder iterations (table EoS)
     uint32_t fallback = 0; // seeded solves whose guess lay outside the bracket
+    uint32_t w = 1;       // added per event: 0 where the evaluation is not counted
+                          // (segment overlaps of the sweeps)
 };
 
 // ---------------------------------------------------------------------------
@@ -124,7 +126,7 @@ template <typename T> struct EosIdeal {
     __device__ __forceinline__ bool fixup(T& E, T& Mx, T& My, T& Mz, T& M2, Counts& cnt) const
     {
         if (!((E > T(0)) & (E <= big_value<T>()) & (M2 <= big_value<T>()))) {
-            cnt.bad++;
+            cnt.bad += cnt.w;
             return false;
         }
         const T Mlim = mmax<T>() * E;
@@ -132,11 +134,12 @@ template <typename T> struct EosIdeal {
             const T s = Math<T>::div(Mlim, Math<T>::sqrt(M2));
             Mx = Mx * s; My = My * s; Mz = Mz * s;
             M2 = Mx * Mx + My * My + Mz * Mz;
-            cnt.floor_++;
+            cnt.floor_ += cnt.w;
         }
         return true;
     }
 
+    // The energy flux (E + p) v_D is M_D: r = 1 / (E + p) at the root.
     template <int D>
     __device__ __forceinline__ void flux_core(T E, T Mx, T My, T Mz, T M2, T F[4]) const
     {
@@ -145,7 +148,7 @@ template <typename T> struct EosIdeal {
         const T p = c * e;
         const T MD = (D == 0) ? Mx : ((D == 1) ? My : Mz);
         const T vD = r * MD;
-        F[0] = (E + p) * vD;
+        F[0] = MD;
         F[1] = Mx * vD;
         F[2] = My * vD;
         F[3] = Mz * vD;
@@ -311,7 +314,7 @@ struct EosTable {
                     const double gp = 1.0 - M2 * dp * iw * iw;
                     const double de = g * Math<double>::rcp(gp);
                     double en = e - de;
-                    cnt.iters++;
+                    cnt.iters += cnt.w;
                     // converged: accept the (small) Newton correction before any bracket test,
                     // which could otherwise reject an iterate sitting on the bracket edge
                     if (fabs(de) <= fmax(kNewtonTol * e, kNewtonAbsTol * E)) {
@@ -336,7 +339,7 @@ struct EosTable {
     __device__ __forceinline__ static double seeded_start(double E, double lo, double e0, Counts& cnt)
     {
         if (e0 > lo && e0 < E) return e0;
-        cnt.fallback++;
+        cnt.fallback += cnt.w;
         return 0.5 * (lo + E);
     }
 
@@ -387,7 +390,7 @@ struct EosTable {
                                           Counts& cnt) const
     {
         if (!((E > 0.0) & (E <= big_value<double>()) & (M2 <= big_value<double>()))) {
-            cnt.bad++;
+            cnt.bad += cnt.w;
             return false;
         }
         const double Mlim = mmax<double>() * E;
@@ -395,7 +398,7 @@ struct EosTable {
             const double s = Mlim / Math<double>::sqrt(M2);
             Mx = Mx * s; My = My * s; Mz = Mz * s;
             M2 = Mx * Mx + My * My + Mz * Mz;
-            cnt.floor_++;
+            cnt.floor_ += cnt.w;
         }
         return true;
     }
@@ -432,7 +435,7 @@ struct EosTable {
         const double w = E + p;
         const double MD = (D == 0) ? Mx : ((D == 1) ? My : Mz);
         const double vD = MD * Math<double>::rcp(w);
-        F[0] = w * vD;
+        F[0] = MD;  // (E + p) v_D
         F[1] = Mx * vD;
         F[2] = My * vD;
         F[3] = Mz * vD;
@@ -530,10 +533,12 @@ __device__ __forceinline__ void hancock(const T um[4], const T u0[4], const T up
 //   F_lf = 1/2 (F_L + F_R) - dx/(2 alpha dt) (U_R - U_L)
 //   F    = 1/2 (F_lw + F_lf)
 // with the local predictor U_L -= dt/dx (F - F_L), U_R -= dt/dx (F_R - F)
-// between stages.  UL and UR are consumed.
+// between stages.  UL and UR are consumed.  Returns G = 2 F = F_lw + F_lf
+// (the average's factor 1/2 is exact and is applied with the flux
+// difference, where it folds into the 1/dx factor).
 // ---------------------------------------------------------------------------
 template <int D, typename T, class Eos>
-__device__ __forceinline__ void musta(T UL[4], T UR[4], int k, const AxisConst<T>& ac, T F[4],
+__device__ __forceinline__ void musta(T UL[4], T UR[4], int k, const AxisConst<T>& ac, T G[4],
                                       const Eos& eos, Counts& cnt)
 {
     for (int l = 1;; l++) {
@@ -544,15 +549,13 @@ __device__ __forceinline__ void musta(T UL[4], T UR[4], int k, const AxisConst<T
         for (int c = 0; c < 4; c++) Us[c] = T(0.5) * (UL[c] + UR[c]) - ac.half_alam * (FR[c] - FL[c]);
         eos.template flux<D>(Us, Flw, cnt);
 #pragma unroll
-        for (int c = 0; c < 4; c++) {
-            const T Flf = T(0.5) * (FL[c] + FR[c]) - (UR[c] - UL[c]) * ac.inv_2alam;
-            F[c] = T(0.5) * (Flw[c] + Flf);
-        }
+        for (int c = 0; c < 4; c++)
+            G[c] = fma(T(0.5), FL[c] + FR[c], fma(-ac.inv_2alam, UR[c] - UL[c], Flw[c]));
         if (l >= k) break;
 #pragma unroll
         for (int c = 0; c < 4; c++) {
-            UL[c] = UL[c] - ac.lam * (F[c] - FL[c]);
-            UR[c] = UR[c] - ac.lam * (FR[c] - F[c]);
+            UL[c] = UL[c] - ac.lam * fma(T(0.5), G[c], -FL[c]);   // F - F_L
+            UR[c] = UR[c] - ac.lam * fma(T(-0.5), G[c], FR[c]);   // F_R - F
         }
     }
 }

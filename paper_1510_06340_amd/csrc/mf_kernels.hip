@@ -226,18 +226,16 @@ __device__ __forceinline__ void sweep_line(const SweepArgs<T>& a, const Eos& eos
         }
 
         // cell j+1; counted once over all segments of the line (cells -1..N)
-        Counts ch;
-        hancock<D, LIM>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, ch);
         const int c1 = j + 1;
-        if (c1 == s0 - 1 ? s0 == 0 : (c1 < s1 || c1 == N)) add_counts(cnt, ch);
+        cnt.w = (c1 == s0 - 1 ? s0 == 0 : (c1 < s1 || c1 == N)) ? 1u : 0u;
+        hancock<D, LIM>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, cnt);
         if (j == s0 - 2) {
             copy4(URt, URp);
             continue;
         }
         // interface j + 1/2; counted once over all segments (interfaces -1/2..N-1/2)
-        Counts cm;
-        musta<D>(URp, ULt, a.k, a.ac, Fn, eos, cm);
-        if (body || s0 == 0) add_counts(cnt, cm);
+        cnt.w = (body || s0 == 0) ? 1u : 0u;
+        musta<D>(URp, ULt, a.k, a.ac, Fn, eos, cnt);
         copy4(URt, URp);
         if (!body) {
 #pragma unroll
@@ -249,7 +247,7 @@ __device__ __forceinline__ void sweep_line(const SweepArgs<T>& a, const Eos& eos
         if (a.mode != SW_WRITE) load4((const T* const*)a.L, ij, Lp);
         if (a.mode == SW_FINAL && a.kind != RK_FIRST) load4(a.u0, ij, ub);
 #pragma unroll
-        for (int c = 0; c < 4; c++) Ld[c] = -(Fn[c] - Fp[c]) * a.ac.inv_dx;
+        for (int c = 0; c < 4; c++) Ld[c] = -(Fn[c] - Fp[c]) * a.ac.inv_2dx;   // Fn, Fp: G = 2 F
         emit_cell<T, JET>(a, eos, ij, w0, Ld, Lp, ub, SE, smax);
 #pragma unroll
         for (int c = 0; c < 4; c++) Fp[c] = Fn[c];
@@ -317,17 +315,15 @@ __device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& e
             load4(a.u, base + ghost(xc, N, a.periodic), w1);
             load4(a.u, base + ghost(xc + 1, N, a.periodic), w2);
             T ULt[4], URt[4];
-            Counts ch;
-            hancock<0, LIM>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, ch);
-            if (valid & (it >= s)) add_counts(cnt, ch);
+            cnt.w = (valid & (it >= s)) ? 1u : 0u;
+            hancock<0, LIM>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, cnt);
             T URl[4];
 #pragma unroll
             for (int c = 0; c < 4; c++) URl[c] = shift_up1(URt[c], carryUR[c]);
             T F[4] = {T(0), T(0), T(0), T(0)};
             if (valid & (x >= 0) & (it >= s - 1)) {   // interface x - 1/2
-                Counts cm;
-                musta<0>(URl, ULt, a.k, a.ac, F, eos, cm);
-                if (it >= s) add_counts(cnt, cm);
+                cnt.w = (it >= s) ? 1u : 0u;
+                musta<0>(URl, ULt, a.k, a.ac, F, eos, cnt);
             }
             T Fl[4];
 #pragma unroll
@@ -336,7 +332,7 @@ __device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& e
                 const int64_t ij = base + (x - 1);
                 T Ld[4], Lp[4] = {T(0), T(0), T(0), T(0)}, ub[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-                for (int c = 0; c < 4; c++) Ld[c] = -(F[c] - Fl[c]) * a.ac.inv_dx;
+                for (int c = 0; c < 4; c++) Ld[c] = -(F[c] - Fl[c]) * a.ac.inv_2dx;   // F, Fl: G = 2 F
                 if (a.mode != SW_WRITE) load4((const T* const*)a.L, ij, Lp);
                 if (a.mode == SW_FINAL && a.kind != RK_FIRST) load4(a.u0, ij, ub);
                 emit_cell<T, false>(a, eos, ij, w0, Ld, Lp, ub, T(0), smax);

@@ -12,7 +12,7 @@ template <typename T> struct AxisConst {
     T half_lam;   // dt / (2 dx_d)        (Hancock half step)
     T half_alam;  // alpha dt / (2 dx_d)  (Lax-Wendroff half step)
     T inv_2alam;  // dx_d / (2 alpha dt)  (Lax-Friedrichs viscosity)
-    T inv_dx;     // 1 / dx_d
+    T inv_2dx;    // 1 / (2 dx_d)         (flux difference of G = 2 F)
 };
 
 // Slots of the per-event device statistics block (uint64 each).

@@ -199,7 +199,7 @@ void set_axis_const(AxisConst<T>& ac, double dt, double dx, double alpha, bool p
     ac.half_lam = (T)(0.5 * lam);
     ac.half_alam = (T)(0.5 * alpha * lam);
     ac.inv_2alam = (T)(1.0 / (2.0 * alpha * lam));
-    ac.inv_dx = (T)(1.0 / dx);
+    ac.inv_2dx = (T)(0.5 / dx);
 }
 
 // Argument block of one axis sweep d of one Runge-Kutta stage of event ev.
