@@ -179,6 +179,14 @@ template <typename T> struct EosIdeal {
         }
     }
 
+    // Fluxes of two independent states.
+    template <int D>
+    __device__ __forceinline__ void flux2(const T uA[4], const T uB[4], T FA[4], T FB[4], Counts& cnt) const
+    {
+        flux<D>(uA, FA, cnt);
+        flux<D>(uB, FB, cnt);
+    }
+
     __device__ __forceinline__ void prim(const T u[4], T& e, T& p, T v[3], T& cs2, Counts& cnt) const
     {
         T E = u[0], Mx = u[1], My = u[2], Mz = u[3];
@@ -264,23 +272,32 @@ struct EosTable {
     // cubic of the first guess is evaluated at once (so the piece's loads are
     // issued together), and lanes outside that piece's bounds redo it with the
     // right piece inside a wave-uniform branch.
+    __device__ __forceinline__ int guess_piece(double e) const
+    {
+        float u = (__builtin_amdgcn_logf((float)e) - lg0) * inv_dlg;  // log2 (about 1 ulp)
+        u = fminf(fmaxf(u, 0.0f), (float)n + 0.5f);                    // also maps NaN to 0
+        return (int)u;                                                 // in [0, n]
+    }
+
+    // The piece of e found by stepping from piece k, and its cubic.
+    __device__ __forceinline__ void walk(double e, int k, double& p, double& dp) const
+    {
+        while (k > 0 && e < piece_ptr(k)[0].x) k--;
+        while (k < n && e >= piece_ptr(k)[0].y) k++;
+        cubic(e, piece_ptr(k)[0], piece_ptr(k)[1], p, dp);
+    }
+
     __device__ __forceinline__ void eval(double e, double& p, double& dp) const
     {
         if (log_uniform) {
-            float u = (__builtin_amdgcn_logf((float)e) - lg0) * inv_dlg;  // log2 (about 1 ulp)
-            u = fminf(fmaxf(u, 0.0f), (float)n + 0.5f);                    // also maps NaN to 0
-            int k = (int)u;                                                // in [0, n]
+            const int k = guess_piece(e);
             const double4* r = piece_ptr(k);
             const double4 a = r[0];
             const double4 b = r[1];
             cubic(e, a, b, p, dp);
             const uint64_t off = lanes_where(e < a.x) | lanes_where(e >= a.y);
             if (off != 0) {
-                if (lane_in(off)) {
-                    while (k > 0 && e < piece_ptr(k)[0].x) k--;
-                    while (k < n && e >= piece_ptr(k)[0].y) k++;
-                    cubic(e, piece_ptr(k)[0], piece_ptr(k)[1], p, dp);
-                }
+                if (lane_in(off)) walk(e, k, p, dp);
             }
         } else {
             int lo = 0, hi = n + 1;  // rec[2 lo].x <= e < rec[2 hi].x
@@ -290,6 +307,29 @@ struct EosTable {
                 else hi = mid;
             }
             cubic(e, piece_ptr(lo)[0], piece_ptr(lo)[1], p, dp);
+        }
+    }
+
+    // eval of two arguments, with the loads of both first-guess pieces
+    // issued before either is used (their latency overlaps).
+    __device__ __forceinline__ void eval2(double eA, double eB, double& pA, double& dpA, double& pB,
+                                          double& dpB) const
+    {
+        if (log_uniform) {
+            const int kA = guess_piece(eA), kB = guess_piece(eB);
+            const double4 aA = piece_ptr(kA)[0], bA = piece_ptr(kA)[1];
+            const double4 aB = piece_ptr(kB)[0], bB = piece_ptr(kB)[1];
+            cubic(eA, aA, bA, pA, dpA);
+            cubic(eB, aB, bB, pB, dpB);
+            const uint64_t offA = lanes_where(eA < aA.x) | lanes_where(eA >= aA.y);
+            const uint64_t offB = lanes_where(eB < aB.x) | lanes_where(eB >= aB.y);
+            if ((offA | offB) != 0) {
+                if (lane_in(offA)) walk(eA, kA, pA, dpA);
+                if (lane_in(offB)) walk(eB, kB, pB, dpB);
+            }
+        } else {
+            eval(eA, pA, dpA);
+            eval(eB, pB, dpB);
         }
     }
 
@@ -303,8 +343,14 @@ struct EosTable {
     __device__ __forceinline__ double solve(double E, double M2, double lo, double e_start, double& p, double& dp,
                                             Counts& cnt) const
     {
-        double e = e_start;  // = E at rest (the bracket [E - M2/E, E] is a point)
-        eval(e, p, dp);
+        eval(e_start, p, dp);
+        return newton(E, M2, lo, e_start, p, dp, cnt);
+    }
+
+    // The iterations of solve from e (p and dp/de at e given).
+    __device__ __forceinline__ double newton(double E, double M2, double lo, double e, double& p, double& dp,
+                                             Counts& cnt) const
+    {
         if (__any(M2 != 0.0)) {  // wavefronts entirely at rest are done
             if (M2 != 0.0) {
                 double hi = E;
@@ -366,7 +412,17 @@ struct EosTable {
     // e, p and dp/de of a state with |M|^2 = M2 (E > 0, |M| < E).
     __device__ __forceinline__ double recover(double E, double M2, double& p, double& dp, Counts& cnt) const
     {
-        double lo = E, e_start = E;
+        double lo, e_start;
+        start(E, M2, lo, e_start, cnt);
+        return solve(E, M2, lo, e_start, p, dp, cnt);
+    }
+
+    // Bracket [lo, E] of the root and the start of the solve: E at rest,
+    // else the seed's guess (see seeded_start) or the bracket midpoint.
+    __device__ __forceinline__ void start(double E, double M2, double& lo, double& e_start, Counts& cnt) const
+    {
+        lo = E;
+        e_start = E;
         if (__any(M2 != 0.0)) {  // wavefronts entirely at rest need no bracket
             const double q = M2 * Math<double>::rcp(E);
             lo = E - q;
@@ -383,7 +439,6 @@ struct EosTable {
                 }
             }
         }
-        return solve(E, M2, lo, e_start, p, dp, cnt);
     }
 
     __device__ __forceinline__ bool fixup(double& E, double& Mx, double& My, double& Mz, double& M2,
@@ -424,6 +479,21 @@ struct EosTable {
         return live;
     }
 
+    // Flux from the recovered pressure.
+    template <int D>
+    __device__ __forceinline__ static void assemble(double E, double Mx, double My, double Mz, double p, bool live,
+                                                    double F[4])
+    {
+        const double MD = (D == 0) ? Mx : ((D == 1) ? My : Mz);
+        const double vD = MD * Math<double>::rcp(E + p);
+        F[0] = MD;  // (E + p) v_D
+        F[1] = Mx * vD;
+        F[2] = My * vD;
+        F[3] = Mz * vD;
+        // a replaced state is at rest (M = 0, so vD = 0): only the pressure term is non-zero
+        F[1 + D] = live ? F[1 + D] + p : 0.0;
+    }
+
     template <int D>
     __device__ __forceinline__ void flux(const double u[4], double F[4], Counts& cnt) const
     {
@@ -432,15 +502,31 @@ struct EosTable {
         const bool live = guard(E, Mx, My, Mz, M2, cnt);
         double p, dp;
         recover(E, M2, p, dp, cnt);
-        const double w = E + p;
-        const double MD = (D == 0) ? Mx : ((D == 1) ? My : Mz);
-        const double vD = MD * Math<double>::rcp(w);
-        F[0] = MD;  // (E + p) v_D
-        F[1] = Mx * vD;
-        F[2] = My * vD;
-        F[3] = Mz * vD;
-        // a replaced state is at rest (M = 0, so vD = 0): only the pressure term is non-zero
-        F[1 + D] = live ? F[1 + D] + p : 0.0;
+        assemble<D>(E, Mx, My, Mz, p, live, F);
+    }
+
+    // Fluxes of two independent states, computed as flux() does but with the
+    // first table lookups of both issued together (eval2): in the sweeps the
+    // lookups are L2 hits whose latency would otherwise be paid twice.
+    template <int D>
+    __device__ __forceinline__ void flux2(const double uA[4], const double uB[4], double FA[4], double FB[4],
+                                          Counts& cnt) const
+    {
+        double EA = uA[0], MxA = uA[1], MyA = uA[2], MzA = uA[3];
+        double EB = uB[0], MxB = uB[1], MyB = uB[2], MzB = uB[3];
+        double M2A = MxA * MxA + MyA * MyA + MzA * MzA;
+        double M2B = MxB * MxB + MyB * MyB + MzB * MzB;
+        const bool liveA = guard(EA, MxA, MyA, MzA, M2A, cnt);
+        const bool liveB = guard(EB, MxB, MyB, MzB, M2B, cnt);
+        double loA, eA, loB, eB;
+        start(EA, M2A, loA, eA, cnt);
+        start(EB, M2B, loB, eB, cnt);
+        double pA, dpA, pB, dpB;
+        eval2(eA, eB, pA, dpA, pB, dpB);
+        newton(EA, M2A, loA, eA, pA, dpA, cnt);
+        newton(EB, M2B, loB, eB, pB, dpB, cnt);
+        assemble<D>(EA, MxA, MyA, MzA, pA, liveA, FA);
+        assemble<D>(EB, MxB, MyB, MzB, pB, liveB, FB);
     }
 
     __device__ __forceinline__ void prim(const double u[4], double& e, double& p, double v[3], double& cs2,
@@ -506,7 +592,20 @@ __device__ __forceinline__ T limiter(T a, T b)
 // (Sec. 2.4: piecewise-linear cell profile, faces U^L = U - Delta/2,
 // U^R = U + Delta/2, both advanced by (dt/2dx)(F(U^L) - F(U^R))).
 // ---------------------------------------------------------------------------
-template <int D, int LIM, typename T, class Eos>
+// PAIRED: evaluate the two face fluxes with Eos::flux2 (overlapped table
+// lookups; more registers), else one after the other.
+template <int D, typename T, class Eos, bool PAIRED>
+__device__ __forceinline__ void flux_pair(const Eos& eos, const T uA[4], const T uB[4], T FA[4], T FB[4], Counts& cnt)
+{
+    if constexpr (PAIRED) {
+        eos.template flux2<D>(uA, uB, FA, FB, cnt);
+    } else {
+        eos.template flux<D>(uA, FA, cnt);
+        eos.template flux<D>(uB, FB, cnt);
+    }
+}
+
+template <int D, int LIM, bool PAIRED, typename T, class Eos>
 __device__ __forceinline__ void hancock(const T um[4], const T u0[4], const T up[4], T half_lam,
                                         T ULt[4], T URt[4], const Eos& eos, Counts& cnt)
 {
@@ -517,8 +616,7 @@ __device__ __forceinline__ void hancock(const T um[4], const T u0[4], const T up
         UL[c] = u0[c] - T(0.5) * slope;
         UR[c] = u0[c] + T(0.5) * slope;
     }
-    eos.template flux<D>(UL, FL, cnt);
-    eos.template flux<D>(UR, FR, cnt);
+    flux_pair<D, T, Eos, PAIRED>(eos, UL, UR, FL, FR, cnt);
 #pragma unroll
     for (int c = 0; c < 4; c++) {
         const T delta = half_lam * (FL[c] - FR[c]);
@@ -537,14 +635,13 @@ __device__ __forceinline__ void hancock(const T um[4], const T u0[4], const T up
 // (the average's factor 1/2 is exact and is applied with the flux
 // difference, where it folds into the 1/dx factor).
 // ---------------------------------------------------------------------------
-template <int D, typename T, class Eos>
+template <int D, bool PAIRED, typename T, class Eos>
 __device__ __forceinline__ void musta(T UL[4], T UR[4], int k, const AxisConst<T>& ac, T G[4],
                                       const Eos& eos, Counts& cnt)
 {
     for (int l = 1;; l++) {
         T FL[4], FR[4], Us[4], Flw[4];
-        eos.template flux<D>(UL, FL, cnt);
-        eos.template flux<D>(UR, FR, cnt);
+        flux_pair<D, T, Eos, PAIRED>(eos, UL, UR, FL, FR, cnt);
 #pragma unroll
         for (int c = 0; c < 4; c++) Us[c] = T(0.5) * (UL[c] + UR[c]) - ac.half_alam * (FR[c] - FL[c]);
         eos.template flux<D>(Us, Flw, cnt);

@@ -228,14 +228,14 @@ __device__ __forceinline__ void sweep_line(const SweepArgs<T>& a, const Eos& eos
         // cell j+1; counted once over all segments of the line (cells -1..N)
         const int c1 = j + 1;
         cnt.w = (c1 == s0 - 1 ? s0 == 0 : (c1 < s1 || c1 == N)) ? 1u : 0u;
-        hancock<D, LIM>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, cnt);
+        hancock<D, LIM, true>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, cnt);
         if (j == s0 - 2) {
             copy4(URt, URp);
             continue;
         }
         // interface j + 1/2; counted once over all segments (interfaces -1/2..N-1/2)
         cnt.w = (body || s0 == 0) ? 1u : 0u;
-        musta<D>(URp, ULt, a.k, a.ac, Fn, eos, cnt);
+        musta<D, true>(URp, ULt, a.k, a.ac, Fn, eos, cnt);
         copy4(URt, URp);
         if (!body) {
 #pragma unroll
@@ -282,6 +282,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_waves
 // writes L for the cell on its left.  All loads and stores are coalesced.
 // A wavefront owns items [s, s + 64 * seg) and starts two items early.
 // ---------------------------------------------------------------------------
+// The x sweep evaluates the face fluxes one after the other: paired table
+// lookups (flux2) need about 14 more registers, which costs the x sweep a
+// wavefront per SIMD (four to three) and more time than the overlap saves.
+constexpr bool kPairX = false;
+
 // Wavefront 'wave' of the x sweep: items [wave * 64 * seg, ...) of the row stream.
 template <typename T, int LIM, class Eos>
 __device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& eos, int64_t wave, int lane,
@@ -316,14 +321,14 @@ __device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& e
             load4(a.u, base + ghost(xc + 1, N, a.periodic), w2);
             T ULt[4], URt[4];
             cnt.w = (valid & (it >= s)) ? 1u : 0u;
-            hancock<0, LIM>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, cnt);
+            hancock<0, LIM, kPairX>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, cnt);
             T URl[4];
 #pragma unroll
             for (int c = 0; c < 4; c++) URl[c] = shift_up1(URt[c], carryUR[c]);
             T F[4] = {T(0), T(0), T(0), T(0)};
             if (valid & (x >= 0) & (it >= s - 1)) {   // interface x - 1/2
                 cnt.w = (it >= s) ? 1u : 0u;
-                musta<0>(URl, ULt, a.k, a.ac, F, eos, cnt);
+                musta<0, kPairX>(URl, ULt, a.k, a.ac, F, eos, cnt);
             }
             T Fl[4];
 #pragma unroll
