@@ -78,20 +78,30 @@ __device__ __forceinline__ void flush_stats(unsigned long long* st, const Counts
 }
 
 
+// What the sweep along axis D does with its flux divergence: the x sweep
+// writes L, the y sweep adds to it, the z sweep finishes the stage.  A
+// compile-time constant, so each kernel holds (and keeps registers for) only
+// the arrays its mode uses.
+template <int D>
+constexpr int sweep_mode()
+{
+    return D == 0 ? SW_WRITE : (D == 1 ? SW_ACCUM : SW_FINAL);
+}
+
 // Output of one cell of an axis sweep: write or accumulate L, or (last axis)
 // add the source, apply the Runge-Kutta combine and track the max speed.
 // uin = U[cell] of the stage input, Lp = L so far, ub = RK base state,
 // SE = energy source of the cell (jet only; jet_source below).
-template <typename T, bool JET, class Eos>
+template <typename T, bool JET, int MODE, class Eos>
 __device__ __forceinline__ void emit_cell(const SweepArgs<T>& a, const Eos& eos, int64_t ij, const T uin[4],
                                           const T Ld[4], const T Lp[4], const T ub[4], T SE, T& smax)
 {
-    if (a.mode == SW_WRITE) {
+    if constexpr (MODE == SW_WRITE) {
 #pragma unroll
         for (int c = 0; c < 4; c++) a.L[c][ij] = Ld[c];
         return;
     }
-    if (a.mode == SW_ACCUM) {
+    if constexpr (MODE == SW_ACCUM) {
 #pragma unroll
         for (int c = 0; c < 4; c++) a.L[c][ij] = Lp[c] + Ld[c];
         return;
@@ -244,11 +254,14 @@ __device__ __forceinline__ void sweep_line(const SweepArgs<T>& a, const Eos& eos
         }
 
         T Ld[4], Lp[4] = {T(0), T(0), T(0), T(0)}, ub[4] = {T(0), T(0), T(0), T(0)};
-        if (a.mode != SW_WRITE) load4((const T* const*)a.L, ij, Lp);
-        if (a.mode == SW_FINAL && a.kind != RK_FIRST) load4(a.u0, ij, ub);
+        constexpr int MODE = sweep_mode<D>();
+        if constexpr (MODE != SW_WRITE) load4((const T* const*)a.L, ij, Lp);
+        if constexpr (MODE == SW_FINAL) {
+            if (a.kind != RK_FIRST) load4(a.u0, ij, ub);
+        }
 #pragma unroll
         for (int c = 0; c < 4; c++) Ld[c] = -(Fn[c] - Fp[c]) * a.ac.inv_2dx;   // Fn, Fp: G = 2 F
-        emit_cell<T, JET>(a, eos, ij, w0, Ld, Lp, ub, SE, smax);
+        emit_cell<T, JET, MODE>(a, eos, ij, w0, Ld, Lp, ub, SE, smax);
 #pragma unroll
         for (int c = 0; c < 4; c++) Fp[c] = Fn[c];
     }
@@ -269,7 +282,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_waves
     Counts cnt;
     T smax = T(0);
     sweep_line<T, D, LIM, Eos, JET>(a, eos, line, (int)blockIdx.y * a.seg, cnt, smax);
-    flush_stats(a.stats, cnt, smax, a.mode == SW_FINAL && a.want_smax);
+    flush_stats(a.stats, cnt, smax, sweep_mode<D>() == SW_FINAL && a.want_smax);
 }
 
 // ---------------------------------------------------------------------------
@@ -338,9 +351,7 @@ __device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& e
                 T Ld[4], Lp[4] = {T(0), T(0), T(0), T(0)}, ub[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
                 for (int c = 0; c < 4; c++) Ld[c] = -(F[c] - Fl[c]) * a.ac.inv_2dx;   // F, Fl: G = 2 F
-                if (a.mode != SW_WRITE) load4((const T* const*)a.L, ij, Lp);
-                if (a.mode == SW_FINAL && a.kind != RK_FIRST) load4(a.u0, ij, ub);
-                emit_cell<T, false>(a, eos, ij, w0, Ld, Lp, ub, T(0), smax);
+                emit_cell<T, false, SW_WRITE>(a, eos, ij, w0, Ld, Lp, ub, T(0), smax);
             }
 #pragma unroll
             for (int c = 0; c < 4; c++) {
@@ -363,7 +374,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Eos::kWaves
     T smax = T(0);
     sweep_x_wave<T, LIM, Eos>(a, eos, ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6, threadIdx.x & 63, cnt,
                               smax);
-    flush_stats(a.stats, cnt, smax, a.mode == SW_FINAL && a.want_smax);
+    flush_stats(a.stats, cnt, smax, false);   // the x sweep writes L only
 }
 
 
@@ -407,7 +418,7 @@ void k_batch_sweep(const SweepArgs<T>* __restrict__ tab, const int64_t* __restri
             const int64_t bx = local % nbx, by = local / nbx;
             sweep_line<T, D, LIM, Eos, JET>(a, eos, bx * blockDim.x + threadIdx.x, (int)by * a.seg, cnt, smax);
         }
-        flush_stats(a.stats, cnt, smax, a.mode == SW_FINAL && a.want_smax);
+        flush_stats(a.stats, cnt, smax, sweep_mode<D>() == SW_FINAL && a.want_smax);
     }
 }
 

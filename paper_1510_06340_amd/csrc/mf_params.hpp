@@ -25,7 +25,8 @@ enum { ST_SMAX = 0, ST_FLOOR = 1, ST_BAD = 2, ST_ITERS = 3, ST_FALLBACK = 4, ST_
 //   RK3_LAST : out = (1/3 u0 + 2/3 u) + 2/3 (dt L)              (U^{n+1}, RK3)
 enum { RK_FIRST = 0, RK2_LAST = 1, RK3_MID = 2, RK3_LAST = 3 };
 
-// Modes of an axis sweep.
+// Modes of an axis sweep (fixed by the axis: x writes L, y adds to it, z
+// finishes the stage).
 enum { SW_WRITE = 0, SW_ACCUM = 1, SW_FINAL = 2 };
 
 template <typename T> struct SweepArgs {
@@ -42,7 +43,6 @@ template <typename T> struct SweepArgs {
     int32_t seg;        // cells per thread along the sweep axis
     int32_t periodic;   // 1: periodic along the sweep axis, 0: outflow
     int32_t k;          // MUSTA stages
-    int32_t mode;       // SW_*
     int32_t kind;       // RK_* (SW_FINAL)
     int32_t want_smax;  // SW_FINAL: reduce the max characteristic speed of out
     int32_t axis_f;     // global axis of the fast line index

@@ -226,7 +226,6 @@ SweepArgs<T> make_sweep_args(const Event& ev, int d, int seg, unsigned long long
     a.seg = seg;
     a.periodic = ev.d.bc[d] == MF_BC_PERIODIC;
     a.k = ev.d.musta_k;
-    a.mode = d == 0 ? SW_WRITE : (d == 1 ? SW_ACCUM : SW_FINAL);
     a.kind = kind;
     a.want_smax = want_smax ? 1 : 0;
     a.axis_f = geo.axis_f;

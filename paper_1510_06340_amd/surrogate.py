@@ -3,7 +3,7 @@
 1. States: crossover-EoS runs of the hot-spot (seed 2), jet (seed 3, with its
    source) and ensemble (seeds 1000+j) workloads at reduced resolution are
    advanced on the GPU; the cell states (E, |M|) of snapshots taken every few
-   steps form the stream from which ``n_samples`` states with |M| > 0 are
+   steps form the stream from which ``n_samples`` states with 0 < |M| < E are
    reservoir-sampled (random keys from a seeded generator, smallest keys kept).
 2. Labels: e and p from the plain bracketed-Newton con2prim (mf_con2prim, MF_C2P_PLAIN).
 3. Network: 2 -> 64 -> 64 -> 1 tanh on x = ((ln E, |M|/E) - mean) / std,
@@ -50,7 +50,7 @@ def _workloads(n):
 
 
 def collect_states(n_samples=1 << 22, seed=42, n=128, snap_every=6, steps=60):
-    """Reservoir sample of (E, |M|) cell states with |M| > 0 from crossover-EoS runs (torch CUDA float64)."""
+    """Reservoir sample of (E, |M|) cell states with 0 < |M| < E from crossover-EoS runs (torch CUDA float64)."""
     import torch
     table, ws = _workloads(n)
     gen = torch.Generator(device="cuda")
@@ -68,7 +68,9 @@ def collect_states(n_samples=1 << 22, seed=42, n=128, snap_every=6, steps=60):
         for _ in range(steps // snap_every):
             g.step(w.dt, snap_every, stats=False)
             Mabs = torch.sqrt(dev[1] ** 2 + dev[2] ** 2 + dev[3] ** 2)
-            sel = Mabs > 0
+            # states the solver sees as they are: moving and subluminal (the guards
+            # clamp |M| >= E, whose root e << E would be a far outlier of ln e)
+            sel = (Mabs > 0) & (Mabs < dev[0])
             k = torch.rand(int(sel.sum()), generator=gen, device="cuda", dtype=torch.float64)
             keys = torch.cat([keys, k])
             E_s = torch.cat([E_s, dev[0][sel]])
