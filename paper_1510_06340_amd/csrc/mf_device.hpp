@@ -232,12 +232,12 @@ struct EosTable {
     float lg0;           // log2 e_0 - (log2 e_{n-1} - log2 e_0) / (n - 1): piece k covers [k, k + 1) in
                          // u = (log2 e - lg0) * inv_dlg
     float inv_dlg;       // (n - 1) / (log2 e_{n-1} - log2 e_0)
-    int32_t max_iter;    // Newton steps at most
+    static constexpr int kMaxIter = 100;  // Newton steps at most
     // learned seed: predictions of the MLP on a grid over (ln E, |M|/E),
     // read by bilinear interpolation (the grid is filled by the MLP kernel)
-    const float* seed;   // [sg0][sg1] or nullptr (plain solve)
-    int32_t sg0, sg1;
-    float seed_lnE0, seed_inv_dlnE;  // grid origin and inverse spacing in ln E
+    // (grid shape and spacing are compile-time constants: fewer scalar
+    // registers in the sweeps)
+    const float* seed;   // [kSeedG0][kSeedG1] or nullptr (plain solve)
     int32_t seed_output;             // 0: grid holds ln e; 1: the bracket fraction (E - e) E / |M|^2
     static constexpr double kSeedMinM2 = 1e-3;  // ln e seed only where (|M|/E)^2 > this
     // Newton stops when |de| <= kNewtonTol e and returns e - de.  The error of
@@ -373,7 +373,7 @@ struct EosTable {
                     if (!(en > lo && en < hi)) en = 0.5 * (lo + hi);
                     e = en;
                     eval(e, p, dp);
-                    if (it >= max_iter) break;  // iteration cap
+                    if (it >= kMaxIter) break;  // iteration cap
                 }
             }
         }
@@ -395,15 +395,17 @@ struct EosTable {
         const float Ef = (float)E;
         const float lnE = __builtin_amdgcn_logf(Ef) * 0.69314718f;
         const float m = __builtin_amdgcn_sqrtf((float)M2) * __builtin_amdgcn_rcpf(Ef);
-        float u = (lnE - seed_lnE0) * seed_inv_dlnE;
-        float v = m * (float)(sg1 - 1);
+        constexpr float lnE0 = (float)kSeedLnLo;
+        constexpr float inv_dlnE = (float)(1.0 / ((kSeedLnHi - kSeedLnLo) / (kSeedG0 - 1)));
+        float u = (lnE - lnE0) * inv_dlnE;
+        float v = m * (float)(kSeedG1 - 1);
         // clamps also map NaN to 0 (fmaxf returns the other operand)
-        u = fminf(fmaxf(u, 0.0f), (float)(sg0 - 1) - 1e-3f);
-        v = fminf(fmaxf(v, 0.0f), (float)(sg1 - 1) - 1e-3f);
+        u = fminf(fmaxf(u, 0.0f), (float)(kSeedG0 - 1) - 1e-3f);
+        v = fminf(fmaxf(v, 0.0f), (float)(kSeedG1 - 1) - 1e-3f);
         const int i = (int)u, j = (int)v;
         const float fu = u - (float)i, fv = v - (float)j;
-        const float* r0 = seed + (int64_t)i * sg1 + j;
-        const float* r1 = r0 + sg1;
+        const float* r0 = seed + i * kSeedG1 + j;
+        const float* r1 = r0 + kSeedG1;
         const float y = (1.0f - fu) * ((1.0f - fv) * r0[0] + fv * r0[1]) + fu * ((1.0f - fv) * r1[0] + fv * r1[1]);
         if (seed_output == 1) return E - (double)y * q;
         return (double)__expf(y);

@@ -15,6 +15,11 @@ template <typename T> struct AxisConst {
     T inv_2dx;    // 1 / (2 dx_d)         (flux difference of G = 2 F)
 };
 
+// Grid of the learned seed's predictions: ln E in [kSeedLnLo, kSeedLnHi]
+// (kSeedG0 points, E from 1e-4 to 1e4) by |M|/E in [0, 1] (kSeedG1 points).
+constexpr int kSeedG0 = 1024, kSeedG1 = 513;
+constexpr double kSeedLnLo = -9.210340371976184, kSeedLnHi = 9.210340371976184;
+
 // Slots of the per-event device statistics block (uint64 each).
 enum { ST_SMAX = 0, ST_FLOOR = 1, ST_BAD = 2, ST_ITERS = 3, ST_FALLBACK = 4, ST_WORDS = 8 };
 

@@ -598,9 +598,7 @@ int batch_prepare_any(mf_grid_s* g, const double* dt)
 }
 
 // Upload the seed network and fill its prediction grid over
-// ln E in [ln 1e-4, ln 1e4] (1024 points) and |M|/E in [0, 1] (513 points).
-constexpr int kSeedG0 = 1024, kSeedG1 = 513;
-constexpr double kSeedLnLo = -9.210340371976184, kSeedLnHi = 9.210340371976184;
+// ln E in [ln 1e-4, ln 1e4] (kSeedG0 points) and |M|/E in [0, 1] (kSeedG1 points).
 
 int install_seed(mf_grid_s* g, const mf_surrogate& s)
 {
@@ -648,10 +646,6 @@ int install_seed(mf_grid_s* g, const mf_surrogate& s)
     g->has_seed = true;
     EosTable& t = g->table;
     t.seed = g->seed_grid;
-    t.sg0 = kSeedG0;
-    t.sg1 = kSeedG1;
-    t.seed_lnE0 = (float)kSeedLnLo;
-    t.seed_inv_dlnE = (float)(1.0 / dl);
     t.seed_output = nrm.output;
     return MF_OK;
 }
@@ -800,7 +794,6 @@ int mf_set_eos(mf_grid_t g, int32_t kind, double cs2, const double* e_tab, const
     t.log_uniform = log_uniform ? 1 : 0;
     t.lg0 = (float)(l0 - dl);  // piece k + 1 starts at node k
     t.inv_dlg = (float)(1.0 / dl);
-    t.max_iter = 100;
     t.seed = nullptr;
     g->eos_kind = MF_EOS_TABLE;
     if (s) {
