@@ -216,14 +216,18 @@ __device__ __forceinline__ void sweep_line(const SweepArgs<T>& a, const Eos& eos
         jet_dxy2 = x * x + y * y;
     }
 
-    T w0[4], w1[4], w2[4];
+    T w0[4], w1[4], w2[4], wn[4];
     T ULt[4], URt[4], URp[4], Fp[4], Fn[4];
     load4(a.u, cell(s0 - 2), w1);
     load4(a.u, cell(s0 - 1), w2);
+    load4(a.u, cell(s0), wn);
     for (int j = s0 - 2; j < s1; j++) {
         copy4(w1, w0);
         copy4(w2, w1);
-        load4(a.u, cell(j + 2), w2);
+        copy4(wn, w2);
+        // cell j+3 is loaded one step ahead (its latency hides behind this step;
+        // the last one, up to cell s1+2, is a ghost index and never used)
+        load4(a.u, cell(j + 3), wn);
         const int64_t ij = base + (int64_t)j * sd;
         const bool body = j >= s0;
         // the jet source of cell j, evaluated here where few values are live
