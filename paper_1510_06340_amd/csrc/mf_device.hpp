@@ -98,6 +98,7 @@ struct Counts {
 //   v_vec = 2 M / ((1+c) E + sqrt((1+c)^2 E^2 - 4 c |M|^2)),  e = E - M.v.
 template <typename T> struct EosIdeal {
     static constexpr int kWaves = 4;  // sweep kernels fit 128 VGPRs without spilling
+    static constexpr bool kLoadLAhead = false;  // no gain at 4 waves; FP32 would lose a wave
     T c;    // cs2
     T qh;   // (1 + cs2) / 2
     T q2q;  // (1 + cs2)^2 / 4
@@ -226,6 +227,7 @@ template <typename T> struct EosIdeal {
 // ---------------------------------------------------------------------------
 struct EosTable {
     static constexpr int kWaves = 2;  // minimum waves per SIMD the sweeps are compiled for (they get 3-4)
+    static constexpr bool kLoadLAhead = true;  // the y sweep loads L ahead (latency-bound at 3 waves)
     const double4* rec;  // 2 (n + 1) records: piece k = rec[2k], rec[2k + 1]
     int32_t n;           // nodes
     int32_t log_uniform; // piece from log2(e) (then a fix-up); else bisection

@@ -230,6 +230,15 @@ __device__ __forceinline__ void sweep_line(const SweepArgs<T>& a, const Eos& eos
         load4(a.u, cell(j + 3), wn);
         const int64_t ij = base + (int64_t)j * sd;
         const bool body = j >= s0;
+        constexpr int MODE = sweep_mode<D>();
+        // With Eos::kLoadLAhead the y sweep's L so far is loaded before the
+        // cell's work, whose latency it hides behind (the z sweep has no
+        // registers to spare)
+        constexpr bool early_L = MODE == SW_ACCUM && Eos::kLoadLAhead;
+        T Lp[4] = {T(0), T(0), T(0), T(0)};
+        if constexpr (early_L) {
+            if (body) load4((const T* const*)a.L, ij, Lp);
+        }
         // the jet source of cell j, evaluated here where few values are live
         T SE = T(0);
         if constexpr (JET && D == 2) {
@@ -257,9 +266,8 @@ __device__ __forceinline__ void sweep_line(const SweepArgs<T>& a, const Eos& eos
             continue;
         }
 
-        T Ld[4], Lp[4] = {T(0), T(0), T(0), T(0)}, ub[4] = {T(0), T(0), T(0), T(0)};
-        constexpr int MODE = sweep_mode<D>();
-        if constexpr (MODE != SW_WRITE) load4((const T* const*)a.L, ij, Lp);
+        T Ld[4], ub[4] = {T(0), T(0), T(0), T(0)};
+        if constexpr (MODE != SW_WRITE && !early_L) load4((const T* const*)a.L, ij, Lp);
         if constexpr (MODE == SW_FINAL) {
             if (a.kind != RK_FIRST) load4(a.u0, ij, ub);
         }
