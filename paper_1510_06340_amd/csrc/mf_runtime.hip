@@ -185,7 +185,10 @@ int auto_chunks_x(const AxisGeom& g, bool table)
 int auto_seg(const AxisGeom& g, bool table)
 {
     const int64_t target_threads = 256LL * 4 * 64 * (table ? 16 : 8);
-    const int64_t min_cells = table ? 8 : 16;
+    int64_t min_cells = table ? 8 : 16;
+    // Small grids (under one wavefront per compute unit at that length) take
+    // segments down to 4 cells: the march's latency, not the overlap, bounds them.
+    if (g.nlines * ((g.N + min_cells - 1) / min_cells) < 256LL * 64) min_cells = 4;
     int64_t nseg = (target_threads + g.nlines - 1) / g.nlines;
     nseg = std::max<int64_t>(1, std::min<int64_t>(nseg, (g.N + min_cells - 1) / min_cells));
     return (int)((g.N + nseg - 1) / nseg);
