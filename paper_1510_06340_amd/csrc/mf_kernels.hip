@@ -179,16 +179,6 @@ __device__ __forceinline__ float shift_up1(float v, float carry)
                                                       false));
 }
 
-__device__ __forceinline__ double lane63(double v)
-{
-    const long long x = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)x, 63);
-    const int hi = __builtin_amdgcn_readlane((int)(x >> 32), 63);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-__device__ __forceinline__ float lane63(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63)); }
-
 // One thread's segment [s0, s0 + seg) of grid line 'line' along axis D.
 template <typename T, int D, int LIM, class Eos, bool JET>
 __device__ __forceinline__ void sweep_line(const SweepArgs<T>& a, const Eos& eos, int64_t line, int s0,
@@ -302,7 +292,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_waves
 // items (row, x), x = -1..N (the cells whose faces feed the N+1 interfaces of
 // the row).  A wavefront takes 64 consecutive items per chunk: each lane
 // reconstructs its cell, receives its left neighbour's right face state by a
-// DPP lane shift (lane 0 from the previous chunk's lane 63), solves the
+// DPP lane shift (lane 0 from the previous chunk's lane 63, through LDS), solves the
 // interface between them, receives the left neighbour's flux the same way and
 // writes L for the cell on its left.  All loads and stores are coalesced.
 // A wavefront owns items [s, s + 64 * seg) and starts two items early.
@@ -313,9 +303,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_waves
 constexpr bool kPairX = false;
 
 // Wavefront 'wave' of the x sweep: items [wave * 64 * seg, ...) of the row stream.
+// carry: this wavefront's 8 LDS slots, through which lane 63 hands its right
+// face state and flux to lane 0 of the next chunk (LDS traffic instead of
+// lane reads into scalar registers and moves back).
 template <typename T, int LIM, class Eos>
 __device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& eos, int64_t wave, int lane,
-                                             Counts& cnt, T& smax)
+                                             T* carry, Counts& cnt, T& smax)
 {
     const int N = a.N;
     const int64_t P = (int64_t)N + 2;
@@ -333,8 +326,11 @@ __device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& e
             x = (int)(it + P) - 1;  // before the first row: never valid
             row = -1;
         }
-        T carryUR[4] = {T(0), T(0), T(0), T(0)};
-        T carryF[4] = {T(0), T(0), T(0), T(0)};
+        if (lane == 63) {
+#pragma unroll
+            for (int c = 0; c < 8; c++) carry[c] = T(0);
+        }
+        __builtin_amdgcn_wave_barrier();
         for (int64_t c0 = s - 2; c0 < e; c0 += 64) {
             it = c0 + lane;
             const bool valid = (it >= 0) & (it < e);
@@ -349,7 +345,7 @@ __device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& e
             hancock<0, LIM, kPairX>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, cnt);
             T URl[4];
 #pragma unroll
-            for (int c = 0; c < 4; c++) URl[c] = shift_up1(URt[c], carryUR[c]);
+            for (int c = 0; c < 4; c++) URl[c] = shift_up1(URt[c], carry[c]);
             T F[4] = {T(0), T(0), T(0), T(0)};
             if (valid & (x >= 0) & (it >= s - 1)) {   // interface x - 1/2
                 cnt.w = (it >= s) ? 1u : 0u;
@@ -357,7 +353,7 @@ __device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& e
             }
             T Fl[4];
 #pragma unroll
-            for (int c = 0; c < 4; c++) Fl[c] = shift_up1(F[c], carryF[c]);
+            for (int c = 0; c < 4; c++) Fl[c] = shift_up1(F[c], carry[4 + c]);
             if (valid & (x >= 1) & (it >= s)) {   // cell x - 1
                 const int64_t ij = base + (x - 1);
                 T Ld[4], Lp[4] = {T(0), T(0), T(0), T(0)}, ub[4] = {T(0), T(0), T(0), T(0)};
@@ -365,11 +361,15 @@ __device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& e
                 for (int c = 0; c < 4; c++) Ld[c] = -(F[c] - Fl[c]) * a.ac.inv_2dx;   // F, Fl: G = 2 F
                 emit_cell<T, false, SW_WRITE>(a, eos, ij, w0, Ld, Lp, ub, T(0), smax);
             }
+            __builtin_amdgcn_wave_barrier();   // every lane has read the carry
+            if (lane == 63) {
 #pragma unroll
-            for (int c = 0; c < 4; c++) {
-                carryUR[c] = lane63(URt[c]);
-                carryF[c] = lane63(F[c]);
+                for (int c = 0; c < 4; c++) {
+                    carry[c] = URt[c];
+                    carry[4 + c] = F[c];
+                }
             }
+            __builtin_amdgcn_wave_barrier();
             x += 64;
             while (x > N) {
                 x -= (int)P;
@@ -382,10 +382,11 @@ __device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& e
 template <typename T, int LIM, class Eos>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Eos::kWaves))) void k_sweep_x(SweepArgs<T> a, Eos eos)
 {
+    __shared__ T carry[256 / 64][8];
     Counts cnt;
     T smax = T(0);
-    sweep_x_wave<T, LIM, Eos>(a, eos, ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6, threadIdx.x & 63, cnt,
-                              smax);
+    sweep_x_wave<T, LIM, Eos>(a, eos, ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6, threadIdx.x & 63,
+                              carry[threadIdx.x >> 6], cnt, smax);
     flush_stats(a.stats, cnt, smax, false);   // the x sweep writes L only
 }
 
@@ -423,8 +424,9 @@ void k_batch_sweep(const SweepArgs<T>* __restrict__ tab, const int64_t* __restri
         Counts cnt;
         T smax = T(0);
         if constexpr (D == 0) {
+            __shared__ T carry[256 / 64][8];
             const int64_t wave = local * (blockDim.x >> 6) + (threadIdx.x >> 6);
-            sweep_x_wave<T, LIM, Eos>(a, eos, wave, threadIdx.x & 63, cnt, smax);
+            sweep_x_wave<T, LIM, Eos>(a, eos, wave, threadIdx.x & 63, carry[threadIdx.x >> 6], cnt, smax);
         } else {
             const int64_t nbx = (a.nlines + blockDim.x - 1) / blockDim.x;
             const int64_t bx = local % nbx, by = local / nbx;
