@@ -573,6 +573,34 @@ hipError_t launch_sweep(int axis, int lim, bool jet, dim3 grid, dim3 block, hipS
     }
 }
 
+template <typename T, int LIM, class Eos>
+static int x_waves_lim(int block)
+{
+    static int w[3] = {0, 0, 0};  // by block size 64 / 128 / 256
+    const int bi = block == 64 ? 0 : (block == 128 ? 1 : 2);
+    if (w[bi] == 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_sweep_x<T, LIM, Eos>),
+                                                         block, 0) != hipSuccess || nb < 1)
+            nb = 1;
+        w[bi] = std::max(1, nb * (block / 64) / 4);
+    }
+    return w[bi];
+}
+
+template <typename T, class Eos>
+int sweep_x_waves(int lim, int block)
+{
+    switch (lim) {
+    case LIM_NONE: return x_waves_lim<T, LIM_NONE, Eos>(block);
+    case LIM_MINMOD: return x_waves_lim<T, LIM_MINMOD, Eos>(block);
+    case LIM_SUPERBEE: return x_waves_lim<T, LIM_SUPERBEE, Eos>(block);
+    case LIM_MC: return x_waves_lim<T, LIM_MC, Eos>(block);
+    case LIM_VANLEER: return x_waves_lim<T, LIM_VANLEER, Eos>(block);
+    default: return x_waves_lim<T, LIM_VANALBADA, Eos>(block);
+    }
+}
+
 template <typename T, class Eos>
 hipError_t launch_con2prim(int64_t n, hipStream_t s, const C2PArgs<T>& a, const Eos& eos)
 {
@@ -691,6 +719,9 @@ template hipError_t launch_sweep<float, EosIdeal<float>>(int, int, bool, dim3, d
                                                          const SweepArgs<float>&, const EosIdeal<float>&);
 template hipError_t launch_sweep<double, EosTable>(int, int, bool, dim3, dim3, hipStream_t,
                                                    const SweepArgs<double>&, const EosTable&);
+template int sweep_x_waves<double, EosIdeal<double>>(int, int);
+template int sweep_x_waves<float, EosIdeal<float>>(int, int);
+template int sweep_x_waves<double, EosTable>(int, int);
 template hipError_t launch_con2prim<double, EosIdeal<double>>(int64_t, hipStream_t, const C2PArgs<double>&,
                                                               const EosIdeal<double>&);
 template hipError_t launch_con2prim<float, EosIdeal<float>>(int64_t, hipStream_t, const C2PArgs<float>&,

@@ -165,13 +165,14 @@ AxisGeom axis_geom(const int32_t n[3], int d)
 }
 
 // x sweep (lanes along x): chunks of 64 row items per wavefront, chosen to
-// give about two rounds of three wavefronts on every SIMD.  With the table
-// EoS the cost per cell varies with the local Newton iterations, and smaller
-// work units (about five rounds) balance it better.
-int auto_chunks_x(const AxisGeom& g, bool table)
+// give about two full rounds of the kernel's resident wavefronts on every
+// SIMD (waves_per_simd, from its occupancy).  With the table EoS the cost per
+// cell varies with the local Newton iterations, and smaller work units (about
+// four rounds) balance it better.
+int auto_chunks_x(const AxisGeom& g, bool table, int waves_per_simd)
 {
     const int64_t items = g.nlines * ((int64_t)g.N + 2);
-    const int64_t target_waves = 256LL * 4 * 3 * (table ? 5 : 2);
+    const int64_t target_waves = 256LL * 4 * waves_per_simd * (table ? 4 : 2);
     int64_t cpw = (items + 64 * target_waves - 1) / (64 * target_waves);
     return (int)std::max<int64_t>(1, std::min<int64_t>(cpw, 64));
 }
@@ -265,10 +266,10 @@ int64_t axis_tiles(const Event& ev, int d, int seg, int block)
     return ((geo.nlines + block - 1) / block) * nseg;
 }
 
-int default_shape(const Event& ev, int d, bool table)
+int default_shape(const Event& ev, int d, bool table, int x_waves)
 {
     const AxisGeom geo = axis_geom(ev.d.n, d);
-    return d == 0 ? auto_chunks_x(geo, table) : auto_seg(geo, table);
+    return d == 0 ? auto_chunks_x(geo, table, x_waves) : auto_seg(geo, table);
 }
 
 template <typename T, class Eos>
@@ -277,7 +278,10 @@ int run_stage(mf_grid_s* g, const Eos& eos, Event& ev, unsigned long long* stats
 {
     for (int d = 0; d < 3; d++) {
         const AxisGeom geo = axis_geom(ev.d.n, d);
-        int seg = g->seg_override[d] > 0 ? g->seg_override[d] : default_shape(ev, d, g->eos_kind == MF_EOS_TABLE);
+        int seg = g->seg_override[d] > 0
+                      ? g->seg_override[d]
+                      : default_shape(ev, d, g->eos_kind == MF_EOS_TABLE,
+                                      d == 0 ? sweep_x_waves<T, Eos>(ev.d.limiter, g->block) : 0);
         if (d > 0) seg = std::min(seg, geo.N);
         SweepArgs<T> a = make_sweep_args<T>(ev, d, seg, stats, uin, u0, out, kind, dt, want_smax);
         const bool jet = ev.jet && d == 2;
