@@ -589,6 +589,45 @@ static int x_waves_lim(int block)
 }
 
 template <typename T, class Eos>
+int sweep_x_waves(int lim, int block);
+
+template <typename T, int D, int LIM, class Eos, bool JET>
+static int yz_waves_lim(int block)
+{
+    static int w[3] = {0, 0, 0};  // by block size 64 / 128 / 256
+    const int bi = block == 64 ? 0 : (block == 128 ? 1 : 2);
+    if (w[bi] == 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, reinterpret_cast<const void*>(&k_sweep<T, D, LIM, Eos, JET>), block, 0) != hipSuccess || nb < 1)
+            nb = 1;
+        w[bi] = std::max(1, nb * (block / 64) / 4);
+    }
+    return w[bi];
+}
+
+template <typename T, int D, class Eos, bool JET>
+static int yz_waves_axis(int lim, int block)
+{
+    switch (lim) {
+    case LIM_NONE: return yz_waves_lim<T, D, LIM_NONE, Eos, JET>(block);
+    case LIM_MINMOD: return yz_waves_lim<T, D, LIM_MINMOD, Eos, JET>(block);
+    case LIM_SUPERBEE: return yz_waves_lim<T, D, LIM_SUPERBEE, Eos, JET>(block);
+    case LIM_MC: return yz_waves_lim<T, D, LIM_MC, Eos, JET>(block);
+    case LIM_VANLEER: return yz_waves_lim<T, D, LIM_VANLEER, Eos, JET>(block);
+    default: return yz_waves_lim<T, D, LIM_VANALBADA, Eos, JET>(block);
+    }
+}
+
+template <typename T, class Eos>
+int sweep_waves_per_simd(int axis, int lim, bool jet, int block)
+{
+    if (axis == 1) return yz_waves_axis<T, 1, Eos, false>(lim, block);
+    if (axis == 2) return jet ? yz_waves_axis<T, 2, Eos, true>(lim, block) : yz_waves_axis<T, 2, Eos, false>(lim, block);
+    return sweep_x_waves<T, Eos>(lim, block);
+}
+
+template <typename T, class Eos>
 int sweep_x_waves(int lim, int block)
 {
     switch (lim) {
@@ -719,9 +758,9 @@ template hipError_t launch_sweep<float, EosIdeal<float>>(int, int, bool, dim3, d
                                                          const SweepArgs<float>&, const EosIdeal<float>&);
 template hipError_t launch_sweep<double, EosTable>(int, int, bool, dim3, dim3, hipStream_t,
                                                    const SweepArgs<double>&, const EosTable&);
-template int sweep_x_waves<double, EosIdeal<double>>(int, int);
-template int sweep_x_waves<float, EosIdeal<float>>(int, int);
-template int sweep_x_waves<double, EosTable>(int, int);
+template int sweep_waves_per_simd<double, EosIdeal<double>>(int, int, bool, int);
+template int sweep_waves_per_simd<float, EosIdeal<float>>(int, int, bool, int);
+template int sweep_waves_per_simd<double, EosTable>(int, int, bool, int);
 template hipError_t launch_con2prim<double, EosIdeal<double>>(int64_t, hipStream_t, const C2PArgs<double>&,
                                                               const EosIdeal<double>&);
 template hipError_t launch_con2prim<float, EosIdeal<float>>(int64_t, hipStream_t, const C2PArgs<float>&,

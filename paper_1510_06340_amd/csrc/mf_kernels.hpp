@@ -17,10 +17,11 @@ hipError_t launch_sweep(int axis, int lim, bool jet, dim3 grid, dim3 block, hipS
 template <typename T, class Eos>
 hipError_t launch_con2prim(int64_t n, hipStream_t s, const C2PArgs<T>& a, const Eos& eos);
 
-// Resident wavefronts per SIMD of the x sweep kernel (from its register and
-// LDS use) at the given block size.
+// Resident wavefronts per SIMD of the sweep kernel along axis (the z kernel
+// with the jet source when jet), from its register and LDS use, at the given
+// block size.
 template <typename T, class Eos>
-int sweep_x_waves(int lim, int block);
+int sweep_waves_per_simd(int axis, int lim, bool jet, int block);
 
 // Deterministic sums of the four components over a.n cells, times dV, into out[4] (device).
 template <typename T>

@@ -177,15 +177,15 @@ int auto_chunks_x(const AxisGeom& g, bool table, int waves_per_simd)
     return (int)std::max<int64_t>(1, std::min<int64_t>(cpw, 64));
 }
 
-// Cells per thread along the sweep axis: enough segments for two rounds of
-// four wavefronts on every SIMD of the 256 compute units (the sweeps run at
-// four wavefronts per SIMD; the second round balances the tail), but at
-// least 16 cells per segment (each segment recomputes two reconstructions
-// and one interface).  With the table EoS (uneven cost per cell): four
-// rounds and at least 8 cells.
-int auto_seg(const AxisGeom& g, bool table)
+// Cells per thread along the sweep axis: enough segments for two full rounds
+// of the kernel's resident wavefronts (waves_per_simd, from its occupancy) on
+// every SIMD of the 256 compute units (the second round balances the tail),
+// but at least 16 cells per segment (each segment recomputes two
+// reconstructions and one interface).  With the table EoS (uneven cost per
+// cell): 16 wavefronts per SIMD (five rounds of three) and at least 8 cells.
+int auto_seg(const AxisGeom& g, bool table, int waves_per_simd)
 {
-    const int64_t target_threads = 256LL * 4 * 64 * (table ? 16 : 8);
+    const int64_t target_threads = 256LL * 4 * 64 * (table ? 16 : 2 * waves_per_simd);
     int64_t min_cells = table ? 8 : 16;
     // Small grids (under one wavefront per compute unit at that length) take
     // segments down to 4 cells: the march's latency, not the overlap, bounds them.
@@ -266,10 +266,10 @@ int64_t axis_tiles(const Event& ev, int d, int seg, int block)
     return ((geo.nlines + block - 1) / block) * nseg;
 }
 
-int default_shape(const Event& ev, int d, bool table, int x_waves)
+int default_shape(const Event& ev, int d, bool table, int waves_per_simd)
 {
     const AxisGeom geo = axis_geom(ev.d.n, d);
-    return d == 0 ? auto_chunks_x(geo, table, x_waves) : auto_seg(geo, table);
+    return d == 0 ? auto_chunks_x(geo, table, waves_per_simd) : auto_seg(geo, table, waves_per_simd);
 }
 
 template <typename T, class Eos>
@@ -281,7 +281,7 @@ int run_stage(mf_grid_s* g, const Eos& eos, Event& ev, unsigned long long* stats
         int seg = g->seg_override[d] > 0
                       ? g->seg_override[d]
                       : default_shape(ev, d, g->eos_kind == MF_EOS_TABLE,
-                                      d == 0 ? sweep_x_waves<T, Eos>(ev.d.limiter, g->block) : 0);
+                                      sweep_waves_per_simd<T, Eos>(d, ev.d.limiter, ev.jet && d == 2, g->block));
         if (d > 0) seg = std::min(seg, geo.N);
         SweepArgs<T> a = make_sweep_args<T>(ev, d, seg, stats, uin, u0, out, kind, dt, want_smax);
         const bool jet = ev.jet && d == 2;
