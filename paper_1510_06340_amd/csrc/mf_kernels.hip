@@ -337,9 +337,19 @@ __device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& e
             const int64_t base = (valid ? row : 0) * (int64_t)N;
             const int xc = valid ? x : 0;
             T w0[4], w1[4], w2[4];
-            load4(a.u, base + ghost(xc - 1, N, a.periodic), w0);
-            load4(a.u, base + ghost(xc, N, a.periodic), w1);
-            load4(a.u, base + ghost(xc + 1, N, a.periodic), w2);
+            // chunks away from row edges (most of them) need no ghost mapping:
+            // the neighbours are the adjacent elements
+            const uint64_t edge = lanes_where(!valid) | lanes_where(xc < 1) | lanes_where(xc > N - 2);
+            if (edge == 0) {
+                const int64_t ic = base + xc;
+                load4(a.u, ic - 1, w0);
+                load4(a.u, ic, w1);
+                load4(a.u, ic + 1, w2);
+            } else {
+                load4(a.u, base + ghost(xc - 1, N, a.periodic), w0);
+                load4(a.u, base + ghost(xc, N, a.periodic), w1);
+                load4(a.u, base + ghost(xc + 1, N, a.periodic), w2);
+            }
             T ULt[4], URt[4];
             cnt.w = (valid & (it >= s)) ? 1u : 0u;
             hancock<0, LIM, kPairX>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, cnt);
