@@ -38,12 +38,13 @@ TRAFFIC_HOTSPOT256_F64 = 1.586e9
 
 # Algorithmic operation counts (add, sub, mul, div, sqrt, min/max each 1 flop).
 C2P_FLUX = 22   # ideal-EoS con2prim + physical flux along one axis (energy flux = M_d)
-LIMITER_OPS = {0: 2, 1: 1, 2: 5, 3: 6, 4: 4, 5: 7}
+LIMITER_OPS = {0: 2, 1: 1, 2: 5, 3: 5, 4: 4, 5: 7}   # MC computes phi / 2 directly (below)
 
 
 def flops_per_cell_axis(k: int, limiter: int) -> int:
     """Reconstruction + Hancock half step + k-stage MUSTA-FORCE + flux difference, per cell and axis."""
-    recon = 4 * (2 + LIMITER_OPS[limiter] + 3)
+    # 2 differences, the limiter, phi / 2 (folded into MC's terms) and the two face values
+    recon = 4 * (2 + LIMITER_OPS[limiter] + (0 if limiter == 3 else 1) + 2)
     hancock = 2 * C2P_FLUX + 4 * 4
     # per stage: Richtmyer state (5 per component) and F_lw + F_lf (6), then the predictor (6)
     musta = k * (3 * C2P_FLUX + 4 * 11) + (k - 1) * 4 * 6
