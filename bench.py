@@ -34,7 +34,7 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector
 # configuration with the default launch shapes, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a 1 GiB device copy (FETCH x 2, WRITE x 1); see
 # profiles/k_sweep_hotspot256_fp64.md.  Other configurations report null.
-TRAFFIC_HOTSPOT256_F64 = 1.586e9
+TRAFFIC_HOTSPOT256_F64 = 1.585e9
 
 # Algorithmic operation counts (add, sub, mul, div, sqrt, min/max each 1 flop).
 C2P_FLUX = 22   # ideal-EoS con2prim + physical flux along one axis (energy flux = M_d)
