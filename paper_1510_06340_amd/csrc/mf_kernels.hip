@@ -1,13 +1,15 @@
 // mf_kernels.hip -- gfx950 kernels of the MUSTA-FORCE step.
 //
 // y and z sweeps (k_sweep): one thread owns a segment of one grid line along
-// the sweep axis and marches along it with a three-cell register window, so
+// the sweep axis and marches along it with a three-cell register window (and
+// the next cell loaded one step ahead), so
 // each cell's reconstruction + Hancock half step and each interface's
 // MUSTA-FORCE flux is computed once (plus two cells and one interface of
 // overlap per segment).  Lanes of a wavefront own neighbouring x cells, so
 // every load and store is one contiguous 512-byte (FP64) row.
 // x sweep (k_sweep_x): lanes lie along x over a stream of row items and pass
-// face states and fluxes to their neighbours by DPP lane shifts.
+// face states and fluxes to their neighbours by DPP lane shifts (across
+// chunks through LDS).
 // The three sweeps of a Runge-Kutta stage accumulate L = ((Lx + Ly) + Lz) in
 // a library-owned array; the z sweep also adds the source term, applies the
 // Runge-Kutta combine and (last stage) reduces the max characteristic speed.
