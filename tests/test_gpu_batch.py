@@ -127,6 +127,23 @@ def test_batch_table_eos_matches_oracle():
     g.free()
 
 
+def test_batch_table_eos_with_jets_matches_oracle():
+    """The tabulated EoS with the jet source (the z sweep's jet variant of the table kernels), batched."""
+    import torch
+    table = I.crossover_table()
+    ws = events(SIZES[:2], jet=True, eos=I.EOS_TABLE)
+    Us = initial(ws)
+    x0 = [(-0.5, 0.1, -0.05), (-0.3, -0.2, 0.1)]
+    g, dev = make_grid(ws, Us, table=table, jets=x0)
+    st = g.batch_step([w.dt for w in ws], 3)
+    torch.cuda.synchronize()
+    for j, w in enumerate(ws):
+        Uo, sto = oracle.step(oracle.Problem.from_workload(w, table=table, jet_x0=x0[j]), Us[j], w.dt, 3)
+        assert max_rel_err(from_dev(dev[j], Us[j].shape[1:]), Uo) <= 1e-10
+        assert st[j]["newton_iters"] > 0 and st[j]["n_bad"] == 0 and st[j]["n_floor"] == sto["n_floor"]
+    g.free()
+
+
 def test_batch_rejects_mixed_limiters():
     ws = events(SIZES[:2])
     ws[1].limiter = I.LIM_MINMOD

@@ -91,6 +91,19 @@ def test_crossover_hotspots_parity_small():
     assert st["smax"] == pytest.approx(sto["smax"], rel=1e-9)
 
 
+def test_crossover_jet_parity():
+    """The tabulated EoS with the jet source (the z sweep's jet variant of the table kernels),
+    per event, from a nonzero start time."""
+    w = I.jet_workload(n=40, steps=5, box=10.0)
+    w.eos = I.EOS_TABLE
+    x0 = (-2.0, 0.3, -0.2)
+    U = I.initial_state(w)
+    Ug, st = gpu_run(w, U, jet_x0=x0, eos_table=TABLE, t0=0.25)
+    Uo, sto = oracle.step(oracle.Problem.from_workload(w, table=TABLE, jet_x0=x0), U, w.dt, w.steps, 0.25)
+    assert max_rel_err(Ug, Uo) <= 1e-10
+    assert st["newton_iters"] > 0 and st["n_bad"] == 0 and st["n_floor"] == sto["n_floor"]
+
+
 @pytest.mark.parametrize("lim", [I.LIM_MINMOD, I.LIM_SUPERBEE, I.LIM_VANLEER])
 def test_crossover_other_limiters_rk3(lim):
     rng = np.random.default_rng(lim)
