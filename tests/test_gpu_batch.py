@@ -144,6 +144,28 @@ def test_batch_table_eos_with_jets_matches_oracle():
     g.free()
 
 
+def test_batch_f32_equals_per_event_and_oracle():
+    """FP32 events, batched: bitwise the per-event FP32 result, and the FP64 oracle to FP32 accuracy."""
+    import torch
+    ws = events(SIZES[:3])
+    Us = initial(ws)
+    gb, devb = make_grid(ws, Us, dtype="f32")
+    gb.batch_step([w.dt for w in ws], 3)
+    torch.cuda.synchronize()
+    for j, w in enumerate(ws):
+        devp = to_dev(Us[j], "f32")
+        gj = mf.Grid([mf.desc_from_workload(w, mf.MF_F32)], [devp])
+        gj.set_eos_ideal()
+        gj.step(w.dt, 3)
+        torch.cuda.synchronize()
+        gj.free()
+        a = from_dev(devb[j], Us[j].shape[1:])
+        assert np.array_equal(a, from_dev(devp, Us[j].shape[1:])), j
+        Uo, _ = oracle.step(oracle.Problem.from_workload(w), Us[j], w.dt, 3)
+        assert float(np.abs(a[0] - Uo[0]).sum() / np.abs(Uo[0]).sum()) <= 1e-5
+    gb.free()
+
+
 def test_batch_rejects_mixed_limiters():
     ws = events(SIZES[:2])
     ws[1].limiter = I.LIM_MINMOD

@@ -227,6 +227,17 @@ def test_fp32_against_fp64_oracle():
     assert st["n_bad"] == 0
 
 
+def test_fp32_jet_against_fp64_oracle():
+    """FP32 with the jet source (the FP32 jet variant of the z sweep) against the FP64 oracle."""
+    w = I.jet_workload(n=48, steps=6, box=12.0)
+    x0 = (-2.0, 0.3, -0.2)
+    U = I.initial_state(w)
+    Ug, st = gpu_run(w, U, dtype="f32", jet_x0=x0, t0=0.5)
+    Uo, _ = oracle_run(w, U, jet_x0=x0, t0=0.5)
+    assert rel_l1_E(Ug, Uo) <= 1e-5
+    assert st["n_bad"] == 0
+
+
 def test_totals_match_oracle():
     from paper_1510_06340_amd import mf
     w = I.hotspot_workload(n=40, box=8.0, steps=3)
