@@ -96,7 +96,8 @@ def run_single(args, w, U, table=None, jet_x0=None):
     from paper_1510_06340_amd import mf
     tdt = torch.float64 if args.dtype == "f64" else torch.float32
     dev = upload(U, tdt)
-    g = mf.Grid([mf.desc_from_workload(w, mf.MF_F64 if args.dtype == "f64" else mf.MF_F32)], [dev])
+    flags = mf.MF_FLAG_UNSPLIT_HANCOCK if args.unsplit_hancock else 0
+    g = mf.Grid([mf.desc_from_workload(w, mf.MF_F64 if args.dtype == "f64" else mf.MF_F32, flags)], [dev])
     if table is None:
         g.set_eos_ideal(w.cs2)
     else:
@@ -201,11 +202,18 @@ def main(argv=None):
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before timing, copy this many MiB device-to-device (a kernel of known traffic "
                          "for scaling hardware byte counters)")
+    ap.add_argument("--unsplit-hancock", action="store_true",
+                    help="hotspot / shock: the unsplit Hancock reading (one correction per cell from all three "
+                         "axes, computed by a pre-pass each stage) instead of the per-axis half step")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU (asked for --gpus {args.gpus}); events shard across "
               "GPUs by event and one large grid by z slabs, which is not built", file=sys.stderr)
+        return 2
+
+    if args.unsplit_hancock and args.workload not in ("hotspot", "shock"):
+        print("bench.py: --unsplit-hancock applies to the hotspot and shock workloads", file=sys.stderr)
         return 2
 
     import torch
@@ -240,6 +248,9 @@ def main(argv=None):
     else:
         w = I.shock_workload()
         desc = "shock tube 200x16x16, e=10|1, minmod, k=2, RK2, dt=0.03"
+    if args.unsplit_hancock:
+        w.extra["unsplit_hancock"] = True
+        desc += "; unsplit Hancock reading (a correction pre-pass over the grid and one ghost layer each stage)"
     if args.steps is None:
         args.steps = w.steps
     U = I.initial_state(w)
@@ -275,7 +286,7 @@ def main(argv=None):
             "frac": achieved_tflops / peak,
             "traffic": (TRAFFIC_HOTSPOT256_F64 if (args.workload == "hotspot" and w.n == (256, 256, 256)
                                                     and args.dtype == "f64" and table is None and args.seg is None
-                                                    and args.block == 256) else None),
+                                                    and args.block == 256 and not args.unsplit_hancock) else None),
             "flops_per_cell_axis": fl_axis,
             "avg_launch_ms": avg_launch_ms,
             "launches": n_launch,
@@ -289,6 +300,8 @@ def main(argv=None):
         },
         "end_state": {"smax": st["smax"], "n_floor": st["n_floor"], "n_bad": st["n_bad"], "E_total": st["totals"][0]},
     }
+    if args.unsplit_hancock:
+        out["roofline"]["prepass_and_gaps_ms_per_step"] = (ms_total - sum(kms)) / args.steps
     if table is not None:
         out["roofline"]["note"] = ("algorithmic flops counted as for p = e/3; the table lookups and Newton "
                                    "iterations of the tabulated EoS are not counted")

@@ -66,6 +66,13 @@ enum mf_c2p_mode {
 #define MF_FLAG_PREDICTOR_ALPHA 2u  /* ablation of the MUSTA predictor coefficient: alpha dt/dx
                                        instead of dt/dx as printed in Sec. 2.4 (the FORCE
                                        fluxes use alpha dt/dx either way) */
+#define MF_FLAG_UNSPLIT_HANCOCK 4u  /* ablation of the multi-dimensional Hancock half step
+                                       (Sec. 2.4 MUSCL-Hancock): one correction per cell,
+                                       sum_d (dt/2dx_d)(F_d(U^{L,d}) - F_d(U^{R,d})) over the three
+                                       axes, added to the faces of every sweep, instead of each
+                                       sweep's own axis term.  mf_step only (mf_batch_step
+                                       returns MF_ERR_ARG); the library allocates
+                                       4 (n0+2)(n1+2)(n2+2) elements per event for it */
 
 typedef struct mf_grid_s* mf_grid_t;
 

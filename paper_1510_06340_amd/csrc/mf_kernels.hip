@@ -182,7 +182,9 @@ __device__ __forceinline__ float shift_up1(float v, float carry)
 }
 
 // One thread's segment [s0, s0 + seg) of grid line 'line' along axis D.
-template <typename T, int D, int LIM, class Eos, bool JET>
+// UNSPLIT (the MF_FLAG_UNSPLIT_HANCOCK ablation): the faces take the cell's
+// three-axis correction from a.dl instead of this axis' Hancock term.
+template <typename T, int D, int LIM, class Eos, bool JET, bool UNSPLIT = false>
 __device__ __forceinline__ void sweep_line(const SweepArgs<T>& a, const Eos& eos, int64_t line, int s0,
                                            Counts& cnt, T& smax)
 {
@@ -192,6 +194,8 @@ __device__ __forceinline__ void sweep_line(const SweepArgs<T>& a, const Eos& eos
     const int64_t i_f = line % a.n_fast;
     const int64_t i_s = line / a.n_fast;
     const int64_t base = i_f * a.stride_f + i_s * a.stride_s;
+    // this line's cells in the extended grid of the unsplit corrections
+    const int64_t ebase = UNSPLIT ? (i_f + 1) * a.estride_f + (i_s + 1) * a.estride_s : 0;
     const int64_t sd = a.stride_d;
     auto cell = [&](int j) -> int64_t { return base + (int64_t)ghost(j, N, a.periodic) * sd; };
 
@@ -243,7 +247,12 @@ __device__ __forceinline__ void sweep_line(const SweepArgs<T>& a, const Eos& eos
         // cell j+1; counted once over all segments of the line (cells -1..N)
         const int c1 = j + 1;
         cnt.w = (c1 == s0 - 1 ? s0 == 0 : (c1 < s1 || c1 == N)) ? 1u : 0u;
-        hancock<D, LIM, true>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, cnt);
+        if constexpr (UNSPLIT) {
+            // cell j+1 in [s0-1, s1], extended coordinate j+2 in [0, N+1]
+            unsplit_faces<LIM>(w0, w1, w2, a.dl + ebase + (int64_t)(j + 2) * a.estride_d, a.dl_n, ULt, URt);
+        } else {
+            hancock<D, LIM, true>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, cnt);
+        }
         if (j == s0 - 2) {
             copy4(URt, URp);
             continue;
@@ -279,13 +288,13 @@ constexpr int sweep_waves()
     return JET && Eos::kWaves > 3 ? 3 : Eos::kWaves;
 }
 
-template <typename T, int D, int LIM, class Eos, bool JET>
+template <typename T, int D, int LIM, class Eos, bool JET, bool UNSPLIT = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_waves<Eos, JET>()))) void k_sweep(SweepArgs<T> a, Eos eos)
 {
     const int64_t line = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     Counts cnt;
     T smax = T(0);
-    sweep_line<T, D, LIM, Eos, JET>(a, eos, line, (int)blockIdx.y * a.seg, cnt, smax);
+    sweep_line<T, D, LIM, Eos, JET, UNSPLIT>(a, eos, line, (int)blockIdx.y * a.seg, cnt, smax);
     flush_stats(a.stats, cnt, smax, sweep_mode<D>() == SW_FINAL && a.want_smax);
 }
 
@@ -308,7 +317,7 @@ constexpr bool kPairX = false;
 // carry: this wavefront's 8 LDS slots, through which lane 63 hands its right
 // face state and flux to lane 0 of the next chunk (LDS traffic instead of
 // lane reads into scalar registers and moves back).
-template <typename T, int LIM, class Eos>
+template <typename T, int LIM, class Eos, bool UNSPLIT = false>
 __device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& eos, int64_t wave, int lane,
                                              T* carry, Counts& cnt, T& smax)
 {
@@ -354,7 +363,15 @@ __device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& e
             }
             T ULt[4], URt[4];
             cnt.w = (valid & (it >= s)) ? 1u : 0u;
-            hancock<0, LIM, kPairX>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, cnt);
+            if constexpr (UNSPLIT) {
+                // the lane's cell xc in [-1, N] of row (y, z) = (r % ny, r / ny), r in [0, ny nz)
+                const int64_t r = valid ? row : 0;
+                const int64_t e = (int64_t)(xc + 1) * a.estride_d + (r % a.n_fast + 1) * a.estride_f +
+                                  (r / a.n_fast + 1) * a.estride_s;
+                unsplit_faces<LIM>(w0, w1, w2, a.dl + e, a.dl_n, ULt, URt);
+            } else {
+                hancock<0, LIM, kPairX>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, cnt);
+            }
             T URl[4];
 #pragma unroll
             for (int c = 0; c < 4; c++) URl[c] = shift_up1(URt[c], carry[c]);
@@ -391,17 +408,70 @@ __device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& e
     }
 }
 
-template <typename T, int LIM, class Eos>
+template <typename T, int LIM, class Eos, bool UNSPLIT = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Eos::kWaves))) void k_sweep_x(SweepArgs<T> a, Eos eos)
 {
     __shared__ T carry[256 / 64][8];
     Counts cnt;
     T smax = T(0);
-    sweep_x_wave<T, LIM, Eos>(a, eos, ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6, threadIdx.x & 63,
+    sweep_x_wave<T, LIM, Eos, UNSPLIT>(a, eos, ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6, threadIdx.x & 63,
                               carry[threadIdx.x >> 6], cnt, smax);
     flush_stats(a.stats, cnt, smax, false);   // the x sweep writes L only
 }
 
+
+// ---------------------------------------------------------------------------
+// Unsplit Hancock corrections (the MF_FLAG_UNSPLIT_HANCOCK ablation), one
+// thread per cell of the grid extended by one ghost cell per side:
+//   dl = sum_d (dt / 2dx_d) (F_d(U^{L,d}) - F_d(U^{R,d})),
+// U^{L,d}, U^{R,d} the limited faces along axis d, the state outside the grid
+// from each axis' boundary condition (ghost indices in [-2, n+1]).
+// ---------------------------------------------------------------------------
+template <int D, int LIM, typename T, class Eos>
+__device__ __forceinline__ void unsplit_axis(const UnsplitArgs<T>& a, const Eos& eos, const int q[3], T delta[4],
+                                             Counts& cnt)
+{
+    T w[3][4];
+#pragma unroll
+    for (int s = 0; s < 3; s++) {
+        int p[3] = {q[0], q[1], q[2]};
+        p[D] += s - 1;
+        const int64_t idx = ghost(p[0], a.n[0], a.periodic[0]) +
+                            (int64_t)a.n[0] * (ghost(p[1], a.n[1], a.periodic[1]) +
+                                               (int64_t)a.n[1] * ghost(p[2], a.n[2], a.periodic[2]));
+#pragma unroll
+        for (int c = 0; c < 4; c++) w[s][c] = a.u[c][idx];
+    }
+    T UL[4], UR[4], FL[4], FR[4];
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        const T hs = half_slope<LIM>(w[1][c] - w[0][c], w[2][c] - w[1][c]);
+        UL[c] = w[1][c] - hs;
+        UR[c] = w[1][c] + hs;
+    }
+    eos.template flux<D>(UL, FL, cnt);
+    eos.template flux<D>(UR, FR, cnt);
+#pragma unroll
+    for (int c = 0; c < 4; c++) delta[c] = delta[c] + a.half_lam[D] * (FL[c] - FR[c]);
+}
+
+template <typename T, int LIM, class Eos>
+__global__ __launch_bounds__(256) void k_unsplit_delta(UnsplitArgs<T> a, Eos eos)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    Counts cnt;
+    if (e < a.dl_n) {
+        const int64_t ex = a.n[0] + 2, ey = a.n[1] + 2;
+        const int q[3] = {(int)(e % ex) - 1, (int)((e / ex) % ey) - 1, (int)(e / (ex * ey)) - 1};
+        T delta[4] = {T(0), T(0), T(0), T(0)};
+        unsplit_axis<0, LIM>(a, eos, q, delta, cnt);
+        unsplit_axis<1, LIM>(a, eos, q, delta, cnt);
+        unsplit_axis<2, LIM>(a, eos, q, delta, cnt);
+#pragma unroll
+        for (int c = 0; c < 4; c++) a.dl[c * a.dl_n + e] = delta[c];
+    }
+    flush_stats(a.stats, cnt, T(0), false);
+}
 
 // ---------------------------------------------------------------------------
 // Batched sweeps: one persistent launch per axis sweep over every event of a
@@ -652,6 +722,49 @@ int sweep_x_waves(int lim, int block)
     }
 }
 
+template <typename T, int LIM, class Eos>
+static hipError_t launch_unsplit_lim(bool jet, int axis, dim3 grid, dim3 block, hipStream_t s, const SweepArgs<T>& a,
+                                     const Eos& eos)
+{
+    if (axis == 0) hipLaunchKernelGGL((k_sweep_x<T, LIM, Eos, true>), grid, block, 0, s, a, eos);
+    else if (axis == 1) hipLaunchKernelGGL((k_sweep<T, 1, LIM, Eos, false, true>), grid, block, 0, s, a, eos);
+    else if (jet) hipLaunchKernelGGL((k_sweep<T, 2, LIM, Eos, true, true>), grid, block, 0, s, a, eos);
+    else hipLaunchKernelGGL((k_sweep<T, 2, LIM, Eos, false, true>), grid, block, 0, s, a, eos);
+    return hipGetLastError();
+}
+
+template <typename T, class Eos>
+hipError_t launch_sweep_unsplit(int axis, int lim, bool jet, dim3 grid, dim3 block, hipStream_t s,
+                                const SweepArgs<T>& a, const Eos& eos)
+{
+    if (axis < 0 || axis > 2) return hipErrorInvalidValue;
+    switch (lim) {
+    case LIM_NONE: return launch_unsplit_lim<T, LIM_NONE>(jet, axis, grid, block, s, a, eos);
+    case LIM_MINMOD: return launch_unsplit_lim<T, LIM_MINMOD>(jet, axis, grid, block, s, a, eos);
+    case LIM_SUPERBEE: return launch_unsplit_lim<T, LIM_SUPERBEE>(jet, axis, grid, block, s, a, eos);
+    case LIM_MC: return launch_unsplit_lim<T, LIM_MC>(jet, axis, grid, block, s, a, eos);
+    case LIM_VANLEER: return launch_unsplit_lim<T, LIM_VANLEER>(jet, axis, grid, block, s, a, eos);
+    case LIM_VANALBADA: return launch_unsplit_lim<T, LIM_VANALBADA>(jet, axis, grid, block, s, a, eos);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, class Eos>
+hipError_t launch_unsplit_delta(int lim, hipStream_t s, const UnsplitArgs<T>& a, const Eos& eos)
+{
+    const dim3 grid((unsigned)((a.dl_n + 255) / 256)), block(256);
+    switch (lim) {
+    case LIM_NONE: hipLaunchKernelGGL((k_unsplit_delta<T, LIM_NONE, Eos>), grid, block, 0, s, a, eos); break;
+    case LIM_MINMOD: hipLaunchKernelGGL((k_unsplit_delta<T, LIM_MINMOD, Eos>), grid, block, 0, s, a, eos); break;
+    case LIM_SUPERBEE: hipLaunchKernelGGL((k_unsplit_delta<T, LIM_SUPERBEE, Eos>), grid, block, 0, s, a, eos); break;
+    case LIM_MC: hipLaunchKernelGGL((k_unsplit_delta<T, LIM_MC, Eos>), grid, block, 0, s, a, eos); break;
+    case LIM_VANLEER: hipLaunchKernelGGL((k_unsplit_delta<T, LIM_VANLEER, Eos>), grid, block, 0, s, a, eos); break;
+    case LIM_VANALBADA: hipLaunchKernelGGL((k_unsplit_delta<T, LIM_VANALBADA, Eos>), grid, block, 0, s, a, eos); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <typename T, class Eos>
 hipError_t launch_con2prim(int64_t n, hipStream_t s, const C2PArgs<T>& a, const Eos& eos)
 {
@@ -773,6 +886,18 @@ template hipError_t launch_sweep<double, EosTable>(int, int, bool, dim3, dim3, h
 template int sweep_waves_per_simd<double, EosIdeal<double>>(int, int, bool, int);
 template int sweep_waves_per_simd<float, EosIdeal<float>>(int, int, bool, int);
 template int sweep_waves_per_simd<double, EosTable>(int, int, bool, int);
+template hipError_t launch_sweep_unsplit<double, EosIdeal<double>>(int, int, bool, dim3, dim3, hipStream_t,
+                                                                   const SweepArgs<double>&, const EosIdeal<double>&);
+template hipError_t launch_sweep_unsplit<float, EosIdeal<float>>(int, int, bool, dim3, dim3, hipStream_t,
+                                                                 const SweepArgs<float>&, const EosIdeal<float>&);
+template hipError_t launch_sweep_unsplit<double, EosTable>(int, int, bool, dim3, dim3, hipStream_t,
+                                                           const SweepArgs<double>&, const EosTable&);
+template hipError_t launch_unsplit_delta<double, EosIdeal<double>>(int, hipStream_t, const UnsplitArgs<double>&,
+                                                                   const EosIdeal<double>&);
+template hipError_t launch_unsplit_delta<float, EosIdeal<float>>(int, hipStream_t, const UnsplitArgs<float>&,
+                                                                 const EosIdeal<float>&);
+template hipError_t launch_unsplit_delta<double, EosTable>(int, hipStream_t, const UnsplitArgs<double>&,
+                                                           const EosTable&);
 template hipError_t launch_con2prim<double, EosIdeal<double>>(int64_t, hipStream_t, const C2PArgs<double>&,
                                                               const EosIdeal<double>&);
 template hipError_t launch_con2prim<float, EosIdeal<float>>(int64_t, hipStream_t, const C2PArgs<float>&,

@@ -17,6 +17,15 @@ hipError_t launch_sweep(int axis, int lim, bool jet, dim3 grid, dim3 block, hipS
 template <typename T, class Eos>
 hipError_t launch_con2prim(int64_t n, hipStream_t s, const C2PArgs<T>& a, const Eos& eos);
 
+// The MF_FLAG_UNSPLIT_HANCOCK ablation: the three-axis Hancock corrections of
+// the stage input over the extended grid (one launch per stage), and the axis
+// sweeps that add them to the faces (a.dl and the extended strides set).
+template <typename T, class Eos>
+hipError_t launch_unsplit_delta(int lim, hipStream_t s, const UnsplitArgs<T>& a, const Eos& eos);
+template <typename T, class Eos>
+hipError_t launch_sweep_unsplit(int axis, int lim, bool jet, dim3 grid, dim3 block, hipStream_t s,
+                                const SweepArgs<T>& a, const Eos& eos);
+
 // Resident wavefronts per SIMD of the sweep kernel along axis (the z kernel
 // with the jet source when jet), from its register and LDS use, at the given
 // block size.

@@ -65,6 +65,22 @@ template <typename T> struct SweepArgs {
     double origin[3];
     double dx[3];
     unsigned long long* stats;  // ST_WORDS per event
+    // unsplit Hancock corrections (MF_FLAG_UNSPLIT_HANCOCK sweeps only): component c of
+    // the extended cell (i, j, k), each in [-1, n], at dl[c * dl_n + ((k+1)(ny+2) + j+1)(nx+2) + i+1]
+    const T* dl;
+    int64_t dl_n;
+    int64_t estride_d, estride_f, estride_s;  // extended strides along the sweep / fast / slow line axes
+};
+
+// Unsplit Hancock corrections over the extended grid (one thread per cell).
+template <typename T> struct UnsplitArgs {
+    const T* u[4];      // stage input state
+    T* dl;              // 4 * dl_n corrections (layout as SweepArgs::dl)
+    int64_t dl_n;
+    int32_t n[3];
+    int32_t periodic[3];
+    T half_lam[3];      // dt / (2 dx_d)
+    unsigned long long* stats;
 };
 
 template <typename T> struct C2PArgs {

@@ -41,6 +41,8 @@ struct Event {
     void* U1[4] = {nullptr, nullptr, nullptr, nullptr};  // RK stage 1 output
     void* U2[4] = {nullptr, nullptr, nullptr, nullptr};  // RK3 stage 2 output
     void* L[4] = {nullptr, nullptr, nullptr, nullptr};   // flux-divergence accumulator
+    void* DL = nullptr;  // MF_FLAG_UNSPLIT_HANCOCK: 4 (n0+2)(n1+2)(n2+2) corrections
+    int64_t dl_n = 0;    // (n0+2)(n1+2)(n2+2)
     double t = 0.0;
     int64_t steps = 0;
     bool jet = false;
@@ -236,6 +238,14 @@ SweepArgs<T> make_sweep_args(const Event& ev, int d, int seg, unsigned long long
     a.axis_s = geo.axis_s;
     set_axis_const(a.ac, dt, ev.d.dx[d], ev.d.alpha, (ev.d.flags & MF_FLAG_PREDICTOR_ALPHA) != 0);
     a.dt = (T)dt;
+    if (ev.DL) {
+        const int64_t es[3] = {1, (int64_t)ev.d.n[0] + 2, ((int64_t)ev.d.n[0] + 2) * ((int64_t)ev.d.n[1] + 2)};
+        a.dl = (const T*)ev.DL;
+        a.dl_n = ev.dl_n;
+        a.estride_d = es[d];
+        a.estride_f = es[geo.axis_f];
+        a.estride_s = es[geo.axis_s];
+    }
     if (ev.jet && d == 2) {
         a.jet_pos[0] = ev.jet_x0[0];
         a.jet_pos[1] = ev.jet_x0[1];
@@ -276,6 +286,21 @@ template <typename T, class Eos>
 int run_stage(mf_grid_s* g, const Eos& eos, Event& ev, unsigned long long* stats, void* const uin[4],
               void* const u0[4], void* const out[4], int kind, double dt, double ts, bool want_smax)
 {
+    if (ev.DL) {  // unsplit Hancock ablation: the three-axis corrections of the stage input
+        UnsplitArgs<T> ua;
+        std::memset(&ua, 0, sizeof(ua));
+        for (int c = 0; c < 4; c++) ua.u[c] = (const T*)uin[c];
+        ua.dl = (T*)ev.DL;
+        ua.dl_n = ev.dl_n;
+        for (int q = 0; q < 3; q++) {
+            ua.n[q] = ev.d.n[q];
+            ua.periodic[q] = ev.d.bc[q] == MF_BC_PERIODIC;
+            ua.half_lam[q] = (T)(0.5 * (dt / ev.d.dx[q]));
+        }
+        ua.stats = stats;
+        hipError_t e = launch_unsplit_delta<T, Eos>(ev.d.limiter, g->stream, ua, eos);
+        if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("unsplit launch: ") + hipGetErrorString(e));
+    }
     for (int d = 0; d < 3; d++) {
         const AxisGeom geo = axis_geom(ev.d.n, d);
         int seg = g->seg_override[d] > 0
@@ -300,7 +325,8 @@ int run_stage(mf_grid_s* g, const Eos& eos, Event& ev, unsigned long long* stats
             MF_HIP(g->take_event(&tm.stop));
             MF_HIP(hipEventRecord(tm.start, g->stream));
         }
-        hipError_t e = launch_sweep<T, Eos>(d, ev.d.limiter, jet, grid, block, g->stream, a, eos);
+        hipError_t e = ev.DL ? launch_sweep_unsplit<T, Eos>(d, ev.d.limiter, jet, grid, block, g->stream, a, eos)
+                             : launch_sweep<T, Eos>(d, ev.d.limiter, jet, grid, block, g->stream, a, eos);
         if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("sweep launch: ") + hipGetErrorString(e));
         if (g->profiling) {
             MF_HIP(hipEventRecord(tm.stop, g->stream));
@@ -672,7 +698,8 @@ int check_desc(const mf_grid_desc& d)
     if (d.musta_k < 1 || d.musta_k > 64) return fail(MF_ERR_ARG, "musta_k must be in [1, 64]");
     if (d.rk_order != 2 && d.rk_order != 3) return fail(MF_ERR_ARG, "rk_order must be 2 or 3");
     if (!(d.alpha > 0.0) || !std::isfinite(d.alpha)) return fail(MF_ERR_ARG, "alpha must be finite and > 0");
-    if (d.flags & ~(MF_FLAG_STRICT | MF_FLAG_PREDICTOR_ALPHA)) return fail(MF_ERR_ARG, "unknown flag bits");
+    if (d.flags & ~(MF_FLAG_STRICT | MF_FLAG_PREDICTOR_ALPHA | MF_FLAG_UNSPLIT_HANCOCK))
+        return fail(MF_ERR_ARG, "unknown flag bits");
     return MF_OK;
 }
 
@@ -709,6 +736,10 @@ int mf_grid_init(mf_grid_t* out, const mf_grid_desc* descs, int32_t n_events, vo
             rc = g->alloc(&ev.U1[c], bytes);
             if (rc == MF_OK) rc = g->alloc(&ev.L[c], bytes);
             if (rc == MF_OK && ev.d.rk_order == 3) rc = g->alloc(&ev.U2[c], bytes);
+        }
+        if (rc == MF_OK && (ev.d.flags & MF_FLAG_UNSPLIT_HANCOCK)) {
+            ev.dl_n = ((int64_t)ev.d.n[0] + 2) * ((int64_t)ev.d.n[1] + 2) * ((int64_t)ev.d.n[2] + 2);
+            rc = g->alloc(&ev.DL, (size_t)ev.dl_n * 4 * elem_size(ev.d.dtype));
         }
     }
     if (rc == MF_OK) rc = g->alloc((void**)&g->dstats, sizeof(unsigned long long) * ST_WORDS * (n_events + 1));
@@ -967,6 +998,8 @@ int mf_batch_step(mf_grid_t g, const double* dt, int32_t nsteps, mf_stats* st)
         const mf_grid_desc& di = g->ev[i].d;
         if (di.dtype != d0.dtype || di.limiter != d0.limiter || di.rk_order != d0.rk_order)
             return fail(MF_ERR_ARG, "batched events must share dtype, limiter and rk_order");
+        if (di.flags & MF_FLAG_UNSPLIT_HANCOCK)
+            return fail(MF_ERR_ARG, "the unsplit Hancock ablation runs with mf_step only");
     }
     int rc = ensure_batch_buffers(g);
     if (rc) return rc;

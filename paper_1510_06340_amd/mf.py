@@ -23,6 +23,7 @@ MF_C2P_PLAIN, MF_C2P_SEEDED, MF_C2P_CONFORMAL = 0, 1, 2
 MF_MLP_HIDDEN, MF_MLP_PARAMS = 64, 4417
 MF_FLAG_STRICT = 1
 MF_FLAG_PREDICTOR_ALPHA = 2
+MF_FLAG_UNSPLIT_HANCOCK = 4
 
 EXPORTS = ["mf_grid_init", "mf_set_eos", "mf_set_source_jet", "mf_set_time", "mf_step", "mf_batch_step",
            "mf_con2prim", "mf_con2prim_stats", "mf_totals", "mf_set_tuning", "mf_set_profiling", "mf_get_profile",

@@ -63,7 +63,7 @@ def _init(lib, desc, ptrs=None):
 @pytest.mark.parametrize("field,value", [
     ("n", (0, 4, 4)), ("n", (65536, 65536, 2)), ("dx", (0.1, 0.0, 0.1)), ("dx", (0.1, float("nan"), 0.1)),
     ("bc", (0, 2, 0)), ("origin", (0.0, float("inf"), 0.0)), ("dtype", 7), ("limiter", 9), ("musta_k", 0),
-    ("musta_k", 65), ("rk_order", 4), ("alpha", -1.0), ("flags", 4)])
+    ("musta_k", 65), ("rk_order", 4), ("alpha", -1.0), ("flags", 8)])
 def test_invalid_descriptors_are_rejected(lib, field, value):
     d = mf.make_desc((4, 4, 4), (0.1, 0.1, 0.1), (0, 0, 0), (0, 0, 0))
     if isinstance(value, tuple):

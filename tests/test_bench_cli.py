@@ -12,3 +12,11 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_unsplit_reading_is_refused_for_event_workloads():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "ensemble",
+                        "--unsplit-hancock"], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "hotspot and shock" in r.stderr
+    assert r.stdout == ""
