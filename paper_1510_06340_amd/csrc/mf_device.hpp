@@ -647,18 +647,24 @@ __device__ __forceinline__ void hancock(const T um[4], const T u0[4], const T up
 
 // Faces of one cell under the unsplit Hancock reading (the ablation of the
 // per-axis step): U^{L,R} = U -/+ phi / 2, both moved by the cell's
-// correction dl (component c at dl[c * dl_n]), which sums the three axes'
-// Hancock terms and is computed once per stage for the whole grid.
+// correction d, which sums the three axes' Hancock terms and is computed once
+// per stage for the whole grid (component c of a cell at dl[c * dl_n]).
+template <typename T>
+__device__ __forceinline__ void load_dl(const T* dl, int64_t dl_n, T d[4])
+{
+#pragma unroll
+    for (int c = 0; c < 4; c++) d[c] = dl[c * dl_n];
+}
+
 template <int LIM, typename T>
-__device__ __forceinline__ void unsplit_faces(const T um[4], const T u0[4], const T up[4], const T* dl, int64_t dl_n,
-                                              T ULt[4], T URt[4])
+__device__ __forceinline__ void unsplit_faces(const T um[4], const T u0[4], const T up[4], const T d[4], T ULt[4],
+                                              T URt[4])
 {
 #pragma unroll
     for (int c = 0; c < 4; c++) {
         const T hs = half_slope<LIM>(u0[c] - um[c], up[c] - u0[c]);
-        const T d = dl[c * dl_n];
-        ULt[c] = (u0[c] - hs) + d;
-        URt[c] = (u0[c] + hs) + d;
+        ULt[c] = (u0[c] - hs) + d[c];
+        URt[c] = (u0[c] + hs) + d[c];
     }
 }
 

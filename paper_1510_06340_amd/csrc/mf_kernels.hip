@@ -248,8 +248,12 @@ __device__ __forceinline__ void sweep_line(const SweepArgs<T>& a, const Eos& eos
         const int c1 = j + 1;
         cnt.w = (c1 == s0 - 1 ? s0 == 0 : (c1 < s1 || c1 == N)) ? 1u : 0u;
         if constexpr (UNSPLIT) {
-            // cell j+1 in [s0-1, s1], extended coordinate j+2 in [0, N+1]
-            unsplit_faces<LIM>(w0, w1, w2, a.dl + ebase + (int64_t)(j + 2) * a.estride_d, a.dl_n, ULt, URt);
+            // cell j+1 in [s0-1, s1], extended coordinate j+2 in [0, N+1].  Loading
+            // it a step ahead like the states was tried: the extra registers
+            // made the z sweep spill, and it ran slower.
+            T d[4];
+            load_dl(a.dl + ebase + (int64_t)(j + 2) * a.estride_d, a.dl_n, d);
+            unsplit_faces<LIM>(w0, w1, w2, d, ULt, URt);
         } else {
             hancock<D, LIM, true>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, cnt);
         }
@@ -368,7 +372,9 @@ __device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& e
                 const int64_t r = valid ? row : 0;
                 const int64_t e = (int64_t)(xc + 1) * a.estride_d + (r % a.n_fast + 1) * a.estride_f +
                                   (r / a.n_fast + 1) * a.estride_s;
-                unsplit_faces<LIM>(w0, w1, w2, a.dl + e, a.dl_n, ULt, URt);
+                T d[4];
+                load_dl(a.dl + e, a.dl_n, d);
+                unsplit_faces<LIM>(w0, w1, w2, d, ULt, URt);
             } else {
                 hancock<0, LIM, kPairX>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, cnt);
             }
@@ -427,27 +433,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Eos::kWaves
 // U^{L,d}, U^{R,d} the limited faces along axis d, the state outside the grid
 // from each axis' boundary condition (ghost indices in [-2, n+1]).
 // ---------------------------------------------------------------------------
+// The seven stencil states are loaded before any flux work so that their
+// latencies overlap; neighbours along axis d differ from the centre in that
+// coordinate only.
 template <int D, int LIM, typename T, class Eos>
-__device__ __forceinline__ void unsplit_axis(const UnsplitArgs<T>& a, const Eos& eos, const int q[3], T delta[4],
-                                             Counts& cnt)
+__device__ __forceinline__ void unsplit_axis(const UnsplitArgs<T>& a, const Eos& eos, const T wm[4], const T w0[4],
+                                             const T wp[4], T delta[4], Counts& cnt)
 {
-    T w[3][4];
-#pragma unroll
-    for (int s = 0; s < 3; s++) {
-        int p[3] = {q[0], q[1], q[2]};
-        p[D] += s - 1;
-        const int64_t idx = ghost(p[0], a.n[0], a.periodic[0]) +
-                            (int64_t)a.n[0] * (ghost(p[1], a.n[1], a.periodic[1]) +
-                                               (int64_t)a.n[1] * ghost(p[2], a.n[2], a.periodic[2]));
-#pragma unroll
-        for (int c = 0; c < 4; c++) w[s][c] = a.u[c][idx];
-    }
     T UL[4], UR[4], FL[4], FR[4];
 #pragma unroll
     for (int c = 0; c < 4; c++) {
-        const T hs = half_slope<LIM>(w[1][c] - w[0][c], w[2][c] - w[1][c]);
-        UL[c] = w[1][c] - hs;
-        UR[c] = w[1][c] + hs;
+        const T hs = half_slope<LIM>(w0[c] - wm[c], wp[c] - w0[c]);
+        UL[c] = w0[c] - hs;
+        UR[c] = w0[c] + hs;
     }
     eos.template flux<D>(UL, FL, cnt);
     eos.template flux<D>(UR, FR, cnt);
@@ -461,12 +459,42 @@ __global__ __launch_bounds__(256) void k_unsplit_delta(UnsplitArgs<T> a, Eos eos
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     Counts cnt;
     if (e < a.dl_n) {
-        const int64_t ex = a.n[0] + 2, ey = a.n[1] + 2;
-        const int q[3] = {(int)(e % ex) - 1, (int)((e / ex) % ey) - 1, (int)(e / (ex * ey)) - 1};
+        const int ex = a.n[0] + 2, ey = a.n[1] + 2;
+        int q[3];
+        if (a.dl_n <= (int64_t)0xffffffffu) {  // wave-uniform: 32-bit index split
+            const uint32_t ue = (uint32_t)e, row = ue / (uint32_t)ex, z = row / (uint32_t)ey;
+            q[0] = (int)(ue - row * (uint32_t)ex) - 1;
+            q[1] = (int)(row - z * (uint32_t)ey) - 1;
+            q[2] = (int)z - 1;
+        } else {
+            const int64_t row = e / ex, z = row / ey;
+            q[0] = (int)(e - row * ex) - 1;
+            q[1] = (int)(row - z * ey) - 1;
+            q[2] = (int)z - 1;
+        }
+        const int64_t stride[3] = {1, (int64_t)a.n[0], (int64_t)a.n[0] * a.n[1]};
+        int g[3], gm[3], gp[3];
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            g[d] = ghost(q[d], a.n[d], a.periodic[d]);
+            gm[d] = ghost(q[d] - 1, a.n[d], a.periodic[d]);
+            gp[d] = ghost(q[d] + 1, a.n[d], a.periodic[d]);
+        }
+        const int64_t i0 = g[0] + stride[1] * g[1] + stride[2] * g[2];
+        T w0[4], wm[3][4], wp[3][4];
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            w0[c] = a.u[c][i0];
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                wm[d][c] = a.u[c][i0 + stride[d] * (gm[d] - g[d])];
+                wp[d][c] = a.u[c][i0 + stride[d] * (gp[d] - g[d])];
+            }
+        }
         T delta[4] = {T(0), T(0), T(0), T(0)};
-        unsplit_axis<0, LIM>(a, eos, q, delta, cnt);
-        unsplit_axis<1, LIM>(a, eos, q, delta, cnt);
-        unsplit_axis<2, LIM>(a, eos, q, delta, cnt);
+        unsplit_axis<0, LIM>(a, eos, wm[0], w0, wp[0], delta, cnt);
+        unsplit_axis<1, LIM>(a, eos, wm[1], w0, wp[1], delta, cnt);
+        unsplit_axis<2, LIM>(a, eos, wm[2], w0, wp[2], delta, cnt);
 #pragma unroll
         for (int c = 0; c < 4; c++) a.dl[c * a.dl_n + e] = delta[c];
     }
