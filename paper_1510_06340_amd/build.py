@@ -23,6 +23,8 @@ FLAGS = [
     # packed FP32 instructions stay off (they are not used on purpose anywhere)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-result",
+    # guards combine side-effect-free compares with '&' / '|' on purpose (no short-circuit branches)
+    "-Wno-bitwise-instead-of-logical",
 ]
 
 
