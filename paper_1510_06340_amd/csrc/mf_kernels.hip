@@ -453,50 +453,56 @@ __device__ __forceinline__ void unsplit_axis(const UnsplitArgs<T>& a, const Eos&
     for (int c = 0; c < 4; c++) delta[c] = delta[c] + a.half_lam[D] * (FL[c] - FR[c]);
 }
 
+// One thread per (x, y) column of the extended grid, marching the extended z
+// planes [z0, z1): the z-1, z and z+1 states stay in registers, so each plane
+// loads its own cell and its four x/y neighbours.  Blocks are dealt to the 8
+// XCDs round-robin; chunk c of 256 columns goes to block 8 (c % per) + c / per,
+// so consecutive chunks (neighbouring rows, whose y neighbours they share)
+// run on one XCD and meet in its L2.  gridDim.x is a multiple of 8.
 template <typename T, int LIM, class Eos>
 __global__ __launch_bounds__(256) void k_unsplit_delta(UnsplitArgs<T> a, Eos eos)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = gridDim.x / 8;
+    const int64_t chunk = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    const int64_t col = chunk * blockDim.x + threadIdx.x;
+    const int64_t ex = a.n[0] + 2, ey = a.n[1] + 2;
+    const int ez = a.n[2] + 2;
+    const int z0 = (int)blockIdx.y * a.zseg;
     Counts cnt;
-    if (e < a.dl_n) {
-        const int ex = a.n[0] + 2, ey = a.n[1] + 2;
-        int q[3];
-        if (a.dl_n <= (int64_t)0xffffffffu) {  // wave-uniform: 32-bit index split
-            const uint32_t ue = (uint32_t)e, row = ue / (uint32_t)ex, z = row / (uint32_t)ey;
-            q[0] = (int)(ue - row * (uint32_t)ex) - 1;
-            q[1] = (int)(row - z * (uint32_t)ey) - 1;
-            q[2] = (int)z - 1;
-        } else {
-            const int64_t row = e / ex, z = row / ey;
-            q[0] = (int)(e - row * ex) - 1;
-            q[1] = (int)(row - z * ey) - 1;
-            q[2] = (int)z - 1;
+    if (col < ex * ey && z0 < ez) {
+        const int z1 = min(z0 + a.zseg, ez);
+        const int64_t row = col / ex;
+        const int q0 = (int)(col - row * ex) - 1, q1 = (int)row - 1;
+        const int64_t sy = a.n[0], sz = (int64_t)a.n[0] * a.n[1];
+        const int g0 = ghost(q0, a.n[0], a.periodic[0]), g1 = ghost(q1, a.n[1], a.periodic[1]);
+        const int64_t cxy = g0 + sy * g1;
+        const int64_t oxm = ghost(q0 - 1, a.n[0], a.periodic[0]) - g0;
+        const int64_t oxp = ghost(q0 + 1, a.n[0], a.periodic[0]) - g0;
+        const int64_t oym = sy * (ghost(q1 - 1, a.n[1], a.periodic[1]) - g1);
+        const int64_t oyp = sy * (ghost(q1 + 1, a.n[1], a.periodic[1]) - g1);
+        auto plane = [&](int q2) -> int64_t { return cxy + sz * ghost(q2, a.n[2], a.periodic[2]); };
+        T zm[4], z0s[4], zp[4];
+        // extended plane ze holds coordinate q2 = ze - 1; its z stencil is q2-1 .. q2+1, all in [-2, n2+1]
+        load4(a.u, plane(z0 - 2), zm);
+        load4(a.u, plane(z0 - 1), z0s);
+        for (int ze = z0; ze < z1; ze++) {
+            const int64_t i0 = plane(ze - 1);
+            T xm[4], xp[4], ym[4], yp[4];
+            load4(a.u, plane(ze), zp);
+            load4(a.u, i0 + oxm, xm);
+            load4(a.u, i0 + oxp, xp);
+            load4(a.u, i0 + oym, ym);
+            load4(a.u, i0 + oyp, yp);
+            T delta[4] = {T(0), T(0), T(0), T(0)};
+            unsplit_axis<0, LIM>(a, eos, xm, z0s, xp, delta, cnt);
+            unsplit_axis<1, LIM>(a, eos, ym, z0s, yp, delta, cnt);
+            unsplit_axis<2, LIM>(a, eos, zm, z0s, zp, delta, cnt);
+            const int64_t e = col + (int64_t)ze * ex * ey;
+#pragma unroll
+            for (int c = 0; c < 4; c++) a.dl[c * a.dl_n + e] = delta[c];
+            copy4(z0s, zm);
+            copy4(zp, z0s);
         }
-        const int64_t stride[3] = {1, (int64_t)a.n[0], (int64_t)a.n[0] * a.n[1]};
-        int g[3], gm[3], gp[3];
-#pragma unroll
-        for (int d = 0; d < 3; d++) {
-            g[d] = ghost(q[d], a.n[d], a.periodic[d]);
-            gm[d] = ghost(q[d] - 1, a.n[d], a.periodic[d]);
-            gp[d] = ghost(q[d] + 1, a.n[d], a.periodic[d]);
-        }
-        const int64_t i0 = g[0] + stride[1] * g[1] + stride[2] * g[2];
-        T w0[4], wm[3][4], wp[3][4];
-#pragma unroll
-        for (int c = 0; c < 4; c++) {
-            w0[c] = a.u[c][i0];
-#pragma unroll
-            for (int d = 0; d < 3; d++) {
-                wm[d][c] = a.u[c][i0 + stride[d] * (gm[d] - g[d])];
-                wp[d][c] = a.u[c][i0 + stride[d] * (gp[d] - g[d])];
-            }
-        }
-        T delta[4] = {T(0), T(0), T(0), T(0)};
-        unsplit_axis<0, LIM>(a, eos, wm[0], w0, wp[0], delta, cnt);
-        unsplit_axis<1, LIM>(a, eos, wm[1], w0, wp[1], delta, cnt);
-        unsplit_axis<2, LIM>(a, eos, wm[2], w0, wp[2], delta, cnt);
-#pragma unroll
-        for (int c = 0; c < 4; c++) a.dl[c * a.dl_n + e] = delta[c];
     }
     flush_stats(a.stats, cnt, T(0), false);
 }
@@ -778,9 +784,14 @@ hipError_t launch_sweep_unsplit(int axis, int lim, bool jet, dim3 grid, dim3 blo
 }
 
 template <typename T, class Eos>
-hipError_t launch_unsplit_delta(int lim, hipStream_t s, const UnsplitArgs<T>& a, const Eos& eos)
+hipError_t launch_unsplit_delta(int lim, hipStream_t s, const UnsplitArgs<T>& a0, const Eos& eos)
 {
-    const dim3 grid((unsigned)((a.dl_n + 255) / 256)), block(256);
+    constexpr int kZSeg = 8;
+    UnsplitArgs<T> a = a0;
+    a.zseg = kZSeg;
+    const int64_t cols = (int64_t)(a.n[0] + 2) * (a.n[1] + 2);
+    const int64_t chunks = (cols + 255) / 256;
+    const dim3 grid((unsigned)(8 * ((chunks + 7) / 8)), (unsigned)((a.n[2] + 2 + kZSeg - 1) / kZSeg)), block(256);
     switch (lim) {
     case LIM_NONE: hipLaunchKernelGGL((k_unsplit_delta<T, LIM_NONE, Eos>), grid, block, 0, s, a, eos); break;
     case LIM_MINMOD: hipLaunchKernelGGL((k_unsplit_delta<T, LIM_MINMOD, Eos>), grid, block, 0, s, a, eos); break;

@@ -72,13 +72,15 @@ template <typename T> struct SweepArgs {
     int64_t estride_d, estride_f, estride_s;  // extended strides along the sweep / fast / slow line axes
 };
 
-// Unsplit Hancock corrections over the extended grid (one thread per cell).
+// Unsplit Hancock corrections over the extended grid (one thread per (x, y)
+// column of it, marching zseg planes).
 template <typename T> struct UnsplitArgs {
     const T* u[4];      // stage input state
     T* dl;              // 4 * dl_n corrections (layout as SweepArgs::dl)
     int64_t dl_n;
     int32_t n[3];
     int32_t periodic[3];
+    int32_t zseg;       // extended z planes per thread (set by the launcher)
     T half_lam[3];      // dt / (2 dx_d)
     unsigned long long* stats;
 };
