@@ -88,3 +88,16 @@ def test_unsplit_is_refused_by_batched_stepping():
     assert ei.value.code == mf.MF_ERR_ARG
     torch.cuda.synchronize()
     g.free()
+
+
+def test_unsplit_with_jet_source():
+    """The unsplit reading with the jet source (the z sweep's jet and unsplit variant), from a nonzero time."""
+    w = I.jet_workload(n=32, steps=4, box=8.0)
+    w.extra["unsplit_hancock"] = True
+    x0 = (-2.0, 0.3, -0.2)
+    U = I.initial_state(w)
+    Ug, st = gpu_run(w, U, jet_x0=x0, t0=0.5, flags=mf.MF_FLAG_UNSPLIT_HANCOCK)
+    prob = oracle.Problem.from_workload(w, jet_x0=x0)
+    Uo, sto = oracle.step(prob, U, w.dt, w.steps, 0.5)
+    assert max_rel_err(Ug, Uo) <= 1e-10
+    assert st["n_floor"] == sto["n_floor"] and st["n_bad"] == 0
