@@ -44,9 +44,10 @@ def test_unsplit_matches_oracle(lim, rk, bc):
 
 
 def test_unsplit_thin_and_ragged_grids():
-    """Lines of 1 and 2 cells (ghost indices wrap or clamp on every side) and a ragged x extent."""
+    """Lines of 1 and 2 cells (ghost indices wrap or clamp on every side), a ragged x extent, and
+    42 x 62 extended columns: 11 chunks of 256, two per XCD group, five idle blocks."""
     rng = np.random.default_rng(5)
-    for n in [(1, 9, 7), (2, 1, 11), (67, 3, 2)]:
+    for n in [(1, 9, 7), (2, 1, 11), (67, 3, 2), (40, 60, 9)]:
         U = moving_state(rng, n, 0.4)
         w = unsplit_workload(n, I.LIM_SUPERBEE, 2, (1, 0, 1))
         Ug, _ = gpu_run(w, U, flags=mf.MF_FLAG_UNSPLIT_HANCOCK)
