@@ -20,6 +20,7 @@
 #include <algorithm>
 
 #include "mf_device.hpp"
+#include "mf_index.hpp"
 #include "mf_kernels.hpp"
 
 namespace mf {
@@ -157,14 +158,6 @@ __device__ __forceinline__ T jet_source(const SweepArgs<T>& a, double r2)
     return SE;
 }
 
-// Ghost cells along a line of N cells: outflow copies the edge cell, periodic
-// wraps (for j in [-2, N+1]; N >= 2 needs one wrap, N == 1 maps to 0).
-__device__ __forceinline__ int ghost(int j, int N, int periodic)
-{
-    if (periodic) return (N == 1) ? 0 : (j < 0 ? j + N : (j >= N ? j - N : j));
-    return j < 0 ? 0 : (j >= N ? N - 1 : j);
-}
-
 // Lane i receives v from lane i-1; lane 0 receives 'carry' (DPP wave shift right).
 __device__ __forceinline__ double shift_up1(double v, double carry)
 {
@@ -221,9 +214,10 @@ __device__ __forceinline__ void sweep_line(const SweepArgs<T>& a, const Eos& eos
         copy4(w1, w0);
         copy4(w2, w1);
         copy4(wn, w2);
-        // cell j+3 is loaded one step ahead (its latency hides behind this step;
-        // the last one, up to cell s1+2, is a ghost index and never used)
-        load4(a.u, cell(j + 3), wn);
+        // cell j+3 is loaded one step ahead (its latency hides behind this
+        // step); march_ahead keeps the last iteration's load, whose value is
+        // never used, inside the line
+        load4(a.u, cell(march_ahead(j, N)), wn);
         const int64_t ij = base + (int64_t)j * sd;
         const bool body = j >= s0;
         constexpr int MODE = sweep_mode<D>();
@@ -335,8 +329,7 @@ __device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& e
         int64_t row = 0;
         int x = 0;
         if (it >= 0) {
-            row = it / P;
-            x = (int)(it - row * P) - 1;
+            x_item(it, N, row, x);
         } else {
             x = (int)(it + P) - 1;  // before the first row: never valid
             row = -1;

@@ -282,8 +282,30 @@ int default_shape(const Event& ev, int d, bool table, int waves_per_simd)
     return d == 0 ? auto_chunks_x(geo, table, waves_per_simd) : auto_seg(geo, table, waves_per_simd);
 }
 
+// What a stage needs besides the event: the stream, launch-shape overrides
+// (0 = automatic), the block size, whether the EoS is tabulated, and the
+// handle that collects kernel timings (nullptr: no timing).
+struct StageCtx {
+    hipStream_t stream;
+    int seg_override[3];
+    int block;
+    bool table;
+    mf_grid_s* prof;
+};
+
+StageCtx stage_ctx(mf_grid_s* g)
+{
+    StageCtx c;
+    c.stream = g->stream;
+    for (int q = 0; q < 3; q++) c.seg_override[q] = g->seg_override[q];
+    c.block = g->block;
+    c.table = g->eos_kind == MF_EOS_TABLE;
+    c.prof = g->profiling ? g : nullptr;
+    return c;
+}
+
 template <typename T, class Eos>
-int run_stage(mf_grid_s* g, const Eos& eos, Event& ev, unsigned long long* stats, void* const uin[4],
+int run_stage(const StageCtx& cx, const Eos& eos, Event& ev, unsigned long long* stats, void* const uin[4],
               void* const u0[4], void* const out[4], int kind, double dt, double ts, bool want_smax)
 {
     if (ev.DL) {  // unsplit Hancock ablation: the three-axis corrections of the stage input
@@ -298,46 +320,46 @@ int run_stage(mf_grid_s* g, const Eos& eos, Event& ev, unsigned long long* stats
             ua.half_lam[q] = (T)(0.5 * (dt / ev.d.dx[q]));
         }
         ua.stats = stats;
-        hipError_t e = launch_unsplit_delta<T, Eos>(ev.d.limiter, g->stream, ua, eos);
+        hipError_t e = launch_unsplit_delta<T, Eos>(ev.d.limiter, cx.stream, ua, eos);
         if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("unsplit launch: ") + hipGetErrorString(e));
     }
     for (int d = 0; d < 3; d++) {
         const AxisGeom geo = axis_geom(ev.d.n, d);
-        int seg = g->seg_override[d] > 0
-                      ? g->seg_override[d]
-                      : default_shape(ev, d, g->eos_kind == MF_EOS_TABLE,
-                                      sweep_waves_per_simd<T, Eos>(d, ev.d.limiter, ev.jet && d == 2, g->block));
+        int seg = cx.seg_override[d] > 0
+                      ? cx.seg_override[d]
+                      : default_shape(ev, d, cx.table,
+                                      sweep_waves_per_simd<T, Eos>(d, ev.d.limiter, ev.jet && d == 2, cx.block));
         if (d > 0) seg = std::min(seg, geo.N);
         SweepArgs<T> a = make_sweep_args<T>(ev, d, seg, stats, uin, u0, out, kind, dt, want_smax);
         const bool jet = ev.jet && d == 2;
         if (jet) a.jet_pos[0] = ev.jet_x0[0] + ev.jet_v * ts;
-        dim3 block(g->block);
+        dim3 block(cx.block);
         dim3 grid;
         if (d == 0) {
-            grid = dim3((unsigned)axis_tiles(ev, 0, a.seg, g->block), 1);
+            grid = dim3((unsigned)axis_tiles(ev, 0, a.seg, cx.block), 1);
         } else {
             const int64_t nseg = (geo.N + a.seg - 1) / a.seg;
-            grid = dim3((unsigned)((geo.nlines + g->block - 1) / g->block), (unsigned)nseg);
+            grid = dim3((unsigned)((geo.nlines + cx.block - 1) / cx.block), (unsigned)nseg);
         }
         mf_grid_s::Timed tm{d, nullptr, nullptr};
-        if (g->profiling) {
-            MF_HIP(g->take_event(&tm.start));
-            MF_HIP(g->take_event(&tm.stop));
-            MF_HIP(hipEventRecord(tm.start, g->stream));
+        if (cx.prof) {
+            MF_HIP(cx.prof->take_event(&tm.start));
+            MF_HIP(cx.prof->take_event(&tm.stop));
+            MF_HIP(hipEventRecord(tm.start, cx.stream));
         }
-        hipError_t e = ev.DL ? launch_sweep_unsplit<T, Eos>(d, ev.d.limiter, jet, grid, block, g->stream, a, eos)
-                             : launch_sweep<T, Eos>(d, ev.d.limiter, jet, grid, block, g->stream, a, eos);
+        hipError_t e = ev.DL ? launch_sweep_unsplit<T, Eos>(d, ev.d.limiter, jet, grid, block, cx.stream, a, eos)
+                             : launch_sweep<T, Eos>(d, ev.d.limiter, jet, grid, block, cx.stream, a, eos);
         if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("sweep launch: ") + hipGetErrorString(e));
-        if (g->profiling) {
-            MF_HIP(hipEventRecord(tm.stop, g->stream));
-            g->timed.push_back(tm);
+        if (cx.prof) {
+            MF_HIP(hipEventRecord(tm.stop, cx.stream));
+            cx.prof->timed.push_back(tm);
         }
     }
     return MF_OK;
 }
 
 template <typename T, class Eos>
-int run_steps_eos(mf_grid_s* g, const Eos& eos, Event& ev, unsigned long long* stats, double dt, int nsteps)
+int run_steps_eos(const StageCtx& g, const Eos& eos, Event& ev, unsigned long long* stats, double dt, int nsteps)
 {
     int rc;
     for (int s = 0; s < nsteps; s++) {
@@ -359,9 +381,10 @@ int run_steps_eos(mf_grid_s* g, const Eos& eos, Event& ev, unsigned long long* s
 
 int run_steps(mf_grid_s* g, Event& ev, unsigned long long* stats, double dt, int nsteps)
 {
-    if (g->eos_kind == MF_EOS_TABLE) return run_steps_eos<double>(g, g->table, ev, stats, dt, nsteps);
-    if (ev.d.dtype == MF_F32) return run_steps_eos<float>(g, EosIdeal<float>::make(g->cs2), ev, stats, dt, nsteps);
-    return run_steps_eos<double>(g, EosIdeal<double>::make(g->cs2), ev, stats, dt, nsteps);
+    const StageCtx cx = stage_ctx(g);
+    if (g->eos_kind == MF_EOS_TABLE) return run_steps_eos<double>(cx, g->table, ev, stats, dt, nsteps);
+    if (ev.d.dtype == MF_F32) return run_steps_eos<float>(cx, EosIdeal<float>::make(g->cs2), ev, stats, dt, nsteps);
+    return run_steps_eos<double>(cx, EosIdeal<double>::make(g->cs2), ev, stats, dt, nsteps);
 }
 
 // Monotone piecewise-cubic node slopes (Fritsch & Carlson 1980), interior
@@ -396,16 +419,54 @@ void monotone_slopes(int n, const double* x, const double* y, std::vector<double
     m[n - 1] = end_slope(h[n - 2], h[n - 3], del[n - 2], del[n - 3]);
 }
 
+// Conservation sums of one event into out[4] (device); partial: 4 kTotalsBlocks doubles (device).
 template <typename T>
-int enqueue_totals(mf_grid_s* g, const Event& ev, double* out)
+int enqueue_totals(hipStream_t stream, double* partial, const Event& ev, double* out)
 {
     TotalsArgs<T> a;
     for (int c = 0; c < 4; c++) a.U[c] = (const T*)ev.U[c];
     a.n = ev.ncell;
-    a.partial = g->dpartial;
+    a.partial = partial;
     const double dV = ev.d.dx[0] * ev.d.dx[1] * ev.d.dx[2];
-    hipError_t e = launch_totals<T>(g->stream, a, kTotalsBlocks, dV, out);
+    hipError_t e = launch_totals<T>(stream, a, kTotalsBlocks, dV, out);
     if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("totals launch: ") + hipGetErrorString(e));
+    return MF_OK;
+}
+
+int enqueue_totals_any(hipStream_t stream, double* partial, const Event& ev, double* out)
+{
+    return ev.d.dtype == MF_F32 ? enqueue_totals<float>(stream, partial, ev, out)
+                                : enqueue_totals<double>(stream, partial, ev, out);
+}
+
+// Host statistics of one event from its device counters w[ST_WORDS] and totals tot[4].
+void fill_stats(const Event& ev, const unsigned long long* w, const double* tot, double dt, mf_stats& s)
+{
+    std::memset(&s, 0, sizeof(s));
+    double smax;
+    std::memcpy(&smax, &w[ST_SMAX], sizeof(double));
+    s.t = ev.t;
+    s.steps = ev.steps;
+    s.smax = smax;
+    const double dxmin = std::min(ev.d.dx[0], std::min(ev.d.dx[1], ev.d.dx[2]));
+    s.courant = smax * dt / dxmin;
+    for (int c = 0; c < 4; c++) s.totals[c] = tot[c];
+    s.n_floor = (int64_t)w[ST_FLOOR];
+    s.n_bad = (int64_t)w[ST_BAD];
+    s.newton_iters = (int64_t)w[ST_ITERS];
+    s.n_fallback = (int64_t)w[ST_FALLBACK];
+}
+
+// MF_FLAG_STRICT verdict of one event's statistics.
+int strict_status(const mf_grid_desc& d, const mf_stats& st, int event)
+{
+    if (!(d.flags & MF_FLAG_STRICT)) return MF_OK;
+    if (st.n_bad > 0 || st.n_floor > 0)
+        return fail(MF_ERR_UNPHYSICAL, "event " + std::to_string(event) + ": unphysical states met (" +
+                                           std::to_string(st.n_bad) + " bad, " + std::to_string(st.n_floor) +
+                                           " clamped)");
+    if (d.alpha * st.courant > 1.0)
+        return fail(MF_ERR_CFL, "event " + std::to_string(event) + ": alpha * Courant number exceeds 1");
     return MF_OK;
 }
 
@@ -911,8 +972,7 @@ static int collect_stats(mf_grid_t g, const double* dts, mf_stats* st)
 {
     const int ne = (int)g->ev.size();
     for (int i = 0; i < ne; i++) {
-        int rc = g->ev[i].d.dtype == MF_F32 ? enqueue_totals<float>(g, g->ev[i], g->dtot + 4 * i)
-                                            : enqueue_totals<double>(g, g->ev[i], g->dtot + 4 * i);
+        int rc = enqueue_totals_any(g->stream, g->dpartial, g->ev[i], g->dtot + 4 * i);
         if (rc) return rc;
     }
     std::vector<unsigned long long> hs((size_t)ST_WORDS * ne);
@@ -921,24 +981,7 @@ static int collect_stats(mf_grid_t g, const double* dts, mf_stats* st)
                           g->stream));
     MF_HIP(hipMemcpyAsync(ht.data(), g->dtot, ht.size() * sizeof(double), hipMemcpyDeviceToHost, g->stream));
     MF_HIP(hipStreamSynchronize(g->stream));
-    for (int i = 0; i < ne; i++) {
-        const Event& ev = g->ev[i];
-        mf_stats& s = st[i];
-        std::memset(&s, 0, sizeof(s));
-        const unsigned long long* w = &hs[(size_t)ST_WORDS * i];
-        double smax;
-        std::memcpy(&smax, &w[ST_SMAX], sizeof(double));
-        s.t = ev.t;
-        s.steps = ev.steps;
-        s.smax = smax;
-        const double dxmin = std::min(ev.d.dx[0], std::min(ev.d.dx[1], ev.d.dx[2]));
-        s.courant = smax * dts[i] / dxmin;
-        for (int c = 0; c < 4; c++) s.totals[c] = ht[4 * i + c];
-        s.n_floor = (int64_t)w[ST_FLOOR];
-        s.n_bad = (int64_t)w[ST_BAD];
-        s.newton_iters = (int64_t)w[ST_ITERS];
-        s.n_fallback = (int64_t)w[ST_FALLBACK];
-    }
+    for (int i = 0; i < ne; i++) fill_stats(g->ev[i], &hs[(size_t)ST_WORDS * i], &ht[4 * i], dts[i], st[i]);
     return MF_OK;
 }
 
@@ -975,13 +1018,8 @@ static int check_strict(mf_grid_t g, const mf_stats* st)
 {
     const int ne = (int)g->ev.size();
     for (int i = 0; i < ne; i++) {
-        if (!(g->ev[i].d.flags & MF_FLAG_STRICT)) continue;
-        if (st[i].n_bad > 0 || st[i].n_floor > 0)
-            return fail(MF_ERR_UNPHYSICAL, "event " + std::to_string(i) + ": unphysical states met (" +
-                                               std::to_string(st[i].n_bad) + " bad, " + std::to_string(st[i].n_floor) +
-                                               " clamped)");
-        if (g->ev[i].d.alpha * st[i].courant > 1.0)
-            return fail(MF_ERR_CFL, "event " + std::to_string(i) + ": alpha * Courant number exceeds 1");
+        const int rc = strict_status(g->ev[i].d, st[i], i);
+        if (rc) return rc;
     }
     return MF_OK;
 }
@@ -1136,8 +1174,7 @@ int mf_totals(mf_grid_t g, int32_t event, double out[4])
     if (!g || !out) return fail(MF_ERR_ARG, "null argument");
     if (event < 0 || event >= (int)g->ev.size()) return fail(MF_ERR_ARG, "event out of range");
     const Event& ev = g->ev[event];
-    int rc = ev.d.dtype == MF_F32 ? enqueue_totals<float>(g, ev, g->dtot + 4 * event)
-                                  : enqueue_totals<double>(g, ev, g->dtot + 4 * event);
+    int rc = enqueue_totals_any(g->stream, g->dpartial, ev, g->dtot + 4 * event);
     if (rc) return rc;
     MF_HIP(hipMemcpyAsync(out, g->dtot + 4 * event, 4 * sizeof(double), hipMemcpyDeviceToHost, g->stream));
     MF_HIP(hipStreamSynchronize(g->stream));

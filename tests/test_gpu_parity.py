@@ -164,6 +164,19 @@ def test_degenerate_and_thin_grids(n):
         assert max_rel_err(Ug, Uo) <= 1e-12
 
 
+@pytest.mark.parametrize("n,bc", [((256, 256, 2), (0, 0, 1)), ((256, 2, 256), (0, 1, 0)), ((64, 2, 2), (1, 1, 1))])
+def test_two_cell_periodic_axes(n, bc):
+    """Periodic axes only two cells thick on wide planes: the y/z march's look-ahead stays
+    inside the line (the last iteration's load is clamped to the last ghost cell)."""
+    rng = np.random.default_rng(n[0] + 3 * n[1] + 7 * n[2])
+    U = random_state(rng, n)
+    w = I.Workload("t", n, (0.1, 0.1, 0.1), (0, 0, 0), bc, I.LIM_MC, 3, 2, 0.02, 2)
+    Ug, st = gpu_run(w, U)
+    Uo, sto = oracle_run(w, U)
+    assert max_rel_err(Ug, Uo) <= 1e-12
+    assert st["n_floor"] == sto["n_floor"] and st["n_bad"] == 0
+
+
 @pytest.mark.parametrize("seg,block", [((1, 1, 1), 64), ((5, 7, 3), 128), ((1000, 1000, 1000), 256), ((2, 16, 16), 64)])
 def test_launch_shapes_agree(seg, block):
     """Every segment length and block size gives the same result (bitwise) and matches the oracle."""
