@@ -47,3 +47,33 @@ def gpu_run(w, U, dtype="f64", nsteps=None, jet_x0=None, eos_table=None, flags=0
         return from_dev(dev, U.shape[1:]), st
     finally:
         g.free()
+
+
+def oracle_block(w, U, lo, size, nsteps, jet_x0=None, table=None, t0=0.0):
+    """The oracle's state after nsteps on the cells [lo, lo + size) (per axis x, y, z) of a grid
+    with outflow boundaries, computed on a sub-block only.
+
+    A Runge-Kutta stage reads two cells along each axis (reconstruction and interface flux), so
+    after nsteps of rk stages a cell depends on the cells within 2 rk nsteps of it.  The block is
+    the requested cells grown by that margin and clipped to the grid: where it meets the grid's
+    faces the outflow rule is the real one; where it is cut inside the grid its own boundary
+    values are wrong, but they reach no requested cell.  The requested cells are therefore those
+    of the full-grid oracle run (the same arithmetic per cell; with the jet source the cell
+    centres are formed from the block's corner, which changes their rounding by an ulp).
+    Returns (oracle state on the requested cells, (z, y, x) slices of them in the full grid)."""
+    import oracle
+    assert all(b == 0 for b in w.bc), "sampled blocks need outflow boundaries"
+    m = 2 * w.rk * nsteps
+    a = [max(0, lo[d] - m) for d in range(3)]
+    b = [min(w.n[d], lo[d] + size[d] + m) for d in range(3)]
+    sub = U[:, a[2]:b[2], a[1]:b[1], a[0]:b[0]]
+    prob = oracle.Problem(n=tuple(b[d] - a[d] for d in range(3)), dx=w.dx,
+                          xlo=tuple(w.xlo[d] + a[d] * w.dx[d] for d in range(3)), bc=w.bc, limiter=w.limiter,
+                          k=w.k, rk=w.rk, alpha=w.alpha, cs2=w.cs2, table=table,
+                          jet=None if jet_x0 is None else dict(x0=jet_x0, v=w.jet["v"], dedx=w.jet["dedx"],
+                                                               sigma=w.jet["sigma"]))
+    V, st = oracle.step(prob, sub, w.dt, nsteps, t0)
+    inner = V[:, lo[2] - a[2]:lo[2] - a[2] + size[2], lo[1] - a[1]:lo[1] - a[1] + size[1],
+              lo[0] - a[0]:lo[0] - a[0] + size[0]]
+    sl = (slice(lo[2], lo[2] + size[2]), slice(lo[1], lo[1] + size[1]), slice(lo[0], lo[0] + size[0]))
+    return inner, sl
