@@ -20,6 +20,10 @@ Backward (the mean squared error over the batch):
 
 bf() rounds to the nearest bfloat16 (ties to even).  With round=False the
 network is the plain float64 one (used for finite-difference checks).
+
+grad_magnitudes() gives, for every gradient element, the sum of the absolute
+values of the terms it sums (the scale of its rounding error), and adam() is
+one Adam step (Kingma and Ba 2015, Algorithm 1) in float64.
 """
 from __future__ import annotations
 
@@ -76,3 +80,34 @@ def loss_and_grads(P, X, t, rnd=True):
     g["W1"] = dz1.T @ X
     g["b1"] = dz1.sum(axis=0)
     return loss, g, y
+
+
+def grad_magnitudes(P, X, t, rnd=True):
+    """Per gradient element, the sum over the batch of |term| of the sum that defines it
+    (the same structure as loss_and_grads, on absolute values)."""
+    y, c = forward(P, X, rnd)
+    B = X.shape[0]
+    r = bf16 if rnd else (lambda a: np.asarray(a, dtype=np.float64))
+    ady = np.abs(2.0 * (y - t) / B)
+    s = {}
+    s["w3"] = np.abs(c["h2"]).T @ ady
+    s["b3"] = float(ady.sum())
+    dz2 = (2.0 * (y - t)[:, None] / B * c["w3"][None, :]) * (1.0 - c["h2"] ** 2)
+    adz2b = np.abs(r(dz2))
+    s["W2"] = adz2b.T @ np.abs(c["h1b"])
+    s["b2"] = np.abs(dz2).sum(axis=0)
+    adz1 = (adz2b @ np.abs(c["W2"])) * (1.0 - c["h1"] ** 2)
+    s["W1"] = adz1.T @ np.abs(X)
+    s["b1"] = adz1.sum(axis=0)
+    return s
+
+
+def adam(P, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step on flat float64 arrays: returns (P, m, v) after it.
+    m <- beta1 m + (1 - beta1) g;  v <- beta2 v + (1 - beta2) g^2;
+    P <- P - lr m_hat / (sqrt(v_hat) + eps), m_hat = m / (1 - beta1^step), v_hat = v / (1 - beta2^step)."""
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** step)
+    vhat = v / (1.0 - beta2 ** step)
+    return P - lr * mhat / (np.sqrt(vhat) + eps), m, v
