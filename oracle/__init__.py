@@ -6,7 +6,8 @@ with gcc into ``liboracle.so`` next to this file) and the exact Riemann solver
 in :mod:`oracle.riemann`.  It shares no code with the HIP library.
 
 Arrays are numpy float64, conserved state shaped (4, nz, ny, nx) with x
-fastest: components (E, Mx, My, Mz).
+fastest: components (E, Mx, My, Mz); with the conserved charge (Problem(charge=True))
+(5, nz, ny, nx), the fifth component being R.
 """
 from __future__ import annotations
 
@@ -22,7 +23,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 LIM_NONE, LIM_MINMOD, LIM_SUPERBEE, LIM_MC, LIM_VANLEER, LIM_VANALBADA = range(6)
 BC_OUTFLOW, BC_PERIODIC = 0, 1
-EOS_IDEAL, EOS_TABLE = 0, 1
+EOS_IDEAL, EOS_TABLE, EOS_GAMMA = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
@@ -43,6 +44,7 @@ class Params(C.Structure):
         ("etab", C.POINTER(C.c_double)), ("ptab", C.POINTER(C.c_double)), ("mtab", C.POINTER(C.c_double)),
         ("jet", C.c_int32), ("jet_x0", C.c_double * 3), ("jet_v", C.c_double), ("jet_dedx", C.c_double),
         ("jet_sigma", C.c_double), ("predictor_alpha", C.c_int32), ("unsplit_hancock", C.c_int32),
+        ("charge", C.c_int32), ("gamma", C.c_double),
     ]
 
 
@@ -69,7 +71,7 @@ def lib():
         L = C.CDLL(_LIB)
         L.ora_pchip_slopes.argtypes = [C.c_int32, _D, _D, _D]
         L.ora_eos_eval.argtypes = [C.POINTER(Params), C.c_int64, _D, _D, _D]
-        L.ora_con2prim.argtypes = [C.POINTER(Params), C.c_int64] + [_D] * 9 + [C.POINTER(Counters)]
+        L.ora_con2prim.argtypes = [C.POINTER(Params), C.c_int64] + [_D] * 11 + [C.POINTER(Counters)]
         L.ora_flux.argtypes = [C.POINTER(Params), C.c_int32, C.c_int64, _D, _D]
         L.ora_limiter.argtypes = [C.c_int32, C.c_int64, _D, _D, _D]
         L.ora_musta.argtypes = [C.POINTER(Params), C.c_int32, C.c_double, C.c_int64, _D, _D, _D]
@@ -98,7 +100,9 @@ class Problem:
 
     def __init__(self, n=(1, 1, 1), dx=(1.0, 1.0, 1.0), xlo=(0.0, 0.0, 0.0), bc=(0, 0, 0),
                  limiter=LIM_MINMOD, k=2, rk=2, alpha=3.0, cs2=1.0 / 3.0, table=None, jet=None,
-                 predictor_alpha=False, unsplit_hancock=False):
+                 predictor_alpha=False, unsplit_hancock=False, charge=False, gamma=None):
+        """charge: carry the conserved charge R as a fifth component (flux R v_d).
+        gamma: the ideal-gas EoS p = (gamma - 1) max(e - n, 0) (needs charge)."""
         self.p = Params()
         self.p.n[:] = [int(v) for v in n]
         self.p.bc[:] = [int(v) for v in bc]
@@ -115,6 +119,12 @@ class Problem:
             self.p.eos = EOS_TABLE
             self.p.ntab = len(e)
             self.p.etab, self.p.ptab, self.p.mtab = _p(e), _p(p), _p(m)
+        self.p.charge = 1 if charge else 0
+        if gamma is not None:
+            if not charge:
+                raise ValueError("the ideal-gas EoS p(e, n) needs the charge")
+            self.p.eos = EOS_GAMMA
+            self.p.gamma = float(gamma)
         self.p.predictor_alpha = 1 if predictor_alpha else 0
         self.p.unsplit_hancock = 1 if unsplit_hancock else 0
         self.p.jet = 0
@@ -131,7 +141,13 @@ class Problem:
         return cls(n=w.n, dx=w.dx, xlo=w.xlo, bc=w.bc, limiter=w.limiter, k=w.k, rk=w.rk,
                    alpha=w.alpha, cs2=w.cs2, table=table, jet=jet,
                    predictor_alpha=w.extra.get("predictor_alpha", False),
-                   unsplit_hancock=w.extra.get("unsplit_hancock", False))
+                   unsplit_hancock=w.extra.get("unsplit_hancock", False),
+                   charge=w.extra.get("charge", False), gamma=w.extra.get("gamma"))
+
+    @property
+    def nc(self):
+        """Conserved components per cell: 5 with the charge, else 4."""
+        return 5 if self.p.charge else 4
 
     @property
     def ref(self):
@@ -153,23 +169,28 @@ def eos(prob: Problem, e):
 
 
 def con2prim(prob: Problem, U):
-    """U: (4, ...) -> (prim (5, ...) = e, p, vx, vy, vz; counters dict)."""
+    """U: (nc, ...) -> (prim (5, ...) = e, p, vx, vy, vz, or (6, ...) with the charge's rest-frame
+    density n last; counters dict)."""
     U = _f64(U)
+    nc = prob.nc
     shape = U.shape[1:]
     n = int(np.prod(shape)) if shape else 1
-    Uf = U.reshape(4, n)
-    comps = [np.ascontiguousarray(Uf[i]) for i in range(4)]
-    out = [np.empty(n) for _ in range(5)]
+    Uf = U.reshape(nc, n)
+    comps = [np.ascontiguousarray(Uf[i]) for i in range(nc)]
+    out = [np.empty(n) for _ in range(nc + 1)]
     cnt = Counters()
-    lib().ora_con2prim(prob.ref, n, *[_p(a) for a in comps], *[_p(a) for a in out], C.byref(cnt))
-    return np.stack(out).reshape((5,) + shape), cnt.as_dict()
+    R = _p(comps[4]) if nc == 5 else None
+    nrest = _p(out[5]) if nc == 5 else None
+    lib().ora_con2prim(prob.ref, n, *[_p(a) for a in comps[:4]], R, *[_p(a) for a in out[:5]], nrest,
+                       C.byref(cnt))
+    return np.stack(out).reshape((nc + 1,) + shape), cnt.as_dict()
 
 
 def flux(prob: Problem, d: int, U):
     U = _f64(U)
     shape = U.shape[1:]
     n = int(np.prod(shape)) if shape else 1
-    Uf = np.ascontiguousarray(U.reshape(4, n))
+    Uf = np.ascontiguousarray(U.reshape(prob.nc, n))
     F = np.empty_like(Uf)
     lib().ora_flux(prob.ref, d, n, _p(Uf), _p(F))
     return F.reshape(U.shape)
@@ -187,7 +208,7 @@ def musta(prob: Problem, d: int, lam: float, UL, UR):
     UL, UR = _f64(UL), _f64(UR)
     shape = UL.shape[1:]
     n = int(np.prod(shape)) if shape else 1
-    l, r = np.ascontiguousarray(UL.reshape(4, n)), np.ascontiguousarray(UR.reshape(4, n))
+    l, r = np.ascontiguousarray(UL.reshape(prob.nc, n)), np.ascontiguousarray(UR.reshape(prob.nc, n))
     F = np.empty_like(l)
     lib().ora_musta(prob.ref, d, lam, n, _p(l), _p(r), _p(F))
     return F.reshape(UL.shape)
@@ -208,7 +229,7 @@ def max_speed(prob: Problem, U) -> float:
 
 def totals(prob: Problem, U) -> np.ndarray:
     U = _f64(U)
-    out = np.empty(4)
+    out = np.empty(prob.nc)
     lib().ora_totals(prob.ref, _p(U), _p(out))
     return out
 

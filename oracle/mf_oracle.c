@@ -50,7 +50,8 @@
 
 enum { LIM_NONE = 0, LIM_MINMOD, LIM_SUPERBEE, LIM_MC, LIM_VANLEER, LIM_VANALBADA };
 enum { BC_OUTFLOW = 0, BC_PERIODIC = 1 };
-enum { EOS_IDEAL = 0, EOS_TABLE = 1 };
+enum { EOS_IDEAL = 0, EOS_TABLE = 1, EOS_GAMMA = 2 };
+#define NCMAX 5 /* E, Mx, My, Mz and the conserved charge R */
 
 #define ORA_MMAX (1.0 - 1e-12) /* largest admitted |M|/E */
 
@@ -79,7 +80,13 @@ typedef struct {
     int32_t unsplit_hancock; /* 1: one Hancock correction per cell from all three axes,
                                 added to all six faces (the alternative reading of the
                                 multi-dimensional MUSCL-Hancock step, Sec. 2.4); 0: per axis */
+    int32_t charge;     /* 1: a fifth conserved component, the charge R = n gamma (Sec. 2.1),
+                           with flux R v_d; 0: U = (E, Mx, My, Mz) */
+    double gamma;       /* EOS_GAMMA: p = (gamma - 1) (e - n), floored at 0 (needs charge) */
 } ora_params;
+
+/* Conserved components per cell. */
+static int ncomp(const ora_params* P) { return P->charge ? 5 : 4; }
 
 typedef struct {
     int64_t n_floor;  /* |M| clamped to (1-1e-12) E */
@@ -189,18 +196,30 @@ void ora_eos_eval(const ora_params* P, int64_t n, const double* e, double* p, do
  * For a tabulated p(e) the same fixed point is the root of
  *   g(e) = e - E + |M|^2 / (E + p(e))
  * on [E (1 - m^2), E], m = |M|/E, found here by bisection.
- * Returns the (possibly clamped) momentum used, through Mu[3]. */
-static void con2prim(const ora_params* P, const double U[4], double prim[5], double Mu[3],
+ * With the charge R (Sec. 2.6, eq. for v): n = R sqrt(1 - v^2).  For p = c e
+ * or the table, p does not depend on n and v is found as above.  For the
+ * ideal gas p(e, n) = (gamma - 1) max(e - n, 0) the fixed point
+ *   v = |M| / (E + p(E - |M| v, R sqrt(1 - v^2)))
+ * is solved by bisection in v on [0, |M|/E] (p >= 0 puts the root there; it
+ * is unique because p -> v = |M| / (E + p) maps the roots one to one onto
+ * those of the decreasing function (gamma - 1)(e(p) - n(p)) - p).
+ * Returns the (possibly clamped) momentum used, through Mu[3];
+ * prim = (e, p, vx, vy, vz, n).  Returns 0 for a state counted as bad
+ * (E <= 0, a non-finite component, or R < 0 with the ideal gas), which is
+ * evaluated as the zero state, else 1. */
+static int con2prim(const ora_params* P, const double* U, double prim[6], double Mu[3],
                      ora_counters* cnt)
 {
     double E = U[0];
     double Mx = U[1], My = U[2], Mz = U[3];
+    double R = P->charge ? U[4] : 0.0;
     cnt->n_calls++;
-    if (!(E > 0.0) || !isfinite(E) || !isfinite(Mx) || !isfinite(My) || !isfinite(Mz)) {
+    if (!(E > 0.0) || !isfinite(E) || !isfinite(Mx) || !isfinite(My) || !isfinite(Mz) || !isfinite(R) ||
+        (P->eos == EOS_GAMMA && !(R >= 0.0))) {
         cnt->n_bad++;
-        prim[0] = 0.0; prim[1] = 0.0; prim[2] = 0.0; prim[3] = 0.0; prim[4] = 0.0;
+        for (int q = 0; q < 6; q++) prim[q] = 0.0;
         Mu[0] = 0.0; Mu[1] = 0.0; Mu[2] = 0.0;
-        return;
+        return 0;
     }
     double M2 = Mx * Mx + My * My + Mz * Mz;
     double Mlim = ORA_MMAX * E;
@@ -222,7 +241,7 @@ static void con2prim(const ora_params* P, const double U[4], double prim[5], dou
         vz = 2.0 * Mz / den;
         e = E - (Mx * vx + My * vy + Mz * vz);
         p = c * e;
-    } else {
+    } else if (P->eos == EOS_TABLE) {
         double lo = E - M2 / E; /* E (1 - m^2) */
         double hi = E;
         double pe, dp;
@@ -242,19 +261,46 @@ static void con2prim(const ora_params* P, const double U[4], double prim[5], dou
         vx = Mx / w;
         vy = My / w;
         vz = Mz / w;
+    } else {
+        const double gm1 = P->gamma - 1.0;
+        const double M = sqrt(M2);
+        double v = 0.0;
+        if (M2 > 0.0) {
+            double lo = 0.0, hi = M / E;
+            int it = 0;
+            while (it < 200) {  /* to the last bit: stop when the midpoint is an end */
+                double mid = 0.5 * (lo + hi);
+                if (!(mid > lo && mid < hi)) break;
+                double pm = gm1 * fmax(E - M * mid - R * sqrt(1.0 - mid * mid), 0.0);
+                if (mid - M / (E + pm) > 0.0) hi = mid; else lo = mid;
+                it++;
+            }
+            cnt->n_iter += it;
+            v = 0.5 * (lo + hi);
+        }
+        e = E - M * v;
+        p = gm1 * fmax(e - R * sqrt(1.0 - v * v), 0.0);
+        double w = E + p;
+        vx = Mx / w;
+        vy = My / w;
+        vz = Mz / w;
     }
     prim[0] = e; prim[1] = p; prim[2] = vx; prim[3] = vy; prim[4] = vz;
+    prim[5] = R * sqrt(1.0 - (vx * vx + vy * vy + vz * vz));
+    return 1;
 }
 
+/* R and n may be NULL (no charge). */
 void ora_con2prim(const ora_params* P, int64_t n, const double* E, const double* Mx,
-                  const double* My, const double* Mz, double* e, double* p, double* vx,
-                  double* vy, double* vz, ora_counters* cnt)
+                  const double* My, const double* Mz, const double* R, double* e, double* p,
+                  double* vx, double* vy, double* vz, double* nrest, ora_counters* cnt)
 {
     ora_counters c = {0, 0, 0, 0};
     for (int64_t i = 0; i < n; i++) {
-        double U[4] = {E[i], Mx[i], My[i], Mz[i]}, pr[5], Mu[3];
+        double U[NCMAX] = {E[i], Mx[i], My[i], Mz[i], R ? R[i] : 0.0}, pr[6], Mu[3];
         con2prim(P, U, pr, Mu, &c);
         e[i] = pr[0]; p[i] = pr[1]; vx[i] = pr[2]; vy[i] = pr[3]; vz[i] = pr[4];
+        if (nrest) nrest[i] = pr[5];
     }
     if (cnt) *cnt = c;
 }
@@ -263,10 +309,14 @@ void ora_con2prim(const ora_params* P, int64_t n, const double* E, const double*
 /* Physical flux along axis d (Sec. 2.1, flux vectors F, G, H)             */
 /* ---------------------------------------------------------------------- */
 
-static void flux(const ora_params* P, int d, const double U[4], double F[4], ora_counters* cnt)
+static void flux(const ora_params* P, int d, const double* U, double* F, ora_counters* cnt)
 {
-    double pr[5], Mu[3];
-    con2prim(P, U, pr, Mu, cnt);
+    double pr[6], Mu[3];
+    const int ncp = ncomp(P);
+    if (!con2prim(P, U, pr, Mu, cnt)) {  /* the zero state: zero flux */
+        for (int q = 0; q < ncp; q++) F[q] = 0.0;
+        return;
+    }
     double p = pr[1];
     double vd = pr[2 + d];
     F[0] = (U[0] + p) * vd;
@@ -274,16 +324,19 @@ static void flux(const ora_params* P, int d, const double U[4], double F[4], ora
     F[2] = Mu[1] * vd;
     F[3] = Mu[2] * vd;
     F[1 + d] = F[1 + d] + p;
+    if (P->charge) F[4] = U[4] * vd;
 }
 
-void ora_flux(const ora_params* P, int32_t d, int64_t n, const double* U /* (4, n) */,
-              double* F /* (4, n) */)
+void ora_flux(const ora_params* P, int32_t d, int64_t n, const double* U /* (nc, n) */,
+              double* F /* (nc, n) */)
 {
     ora_counters c = {0, 0, 0, 0};
+    const int ncp = ncomp(P);
     for (int64_t i = 0; i < n; i++) {
-        double u[4] = {U[i], U[n + i], U[2 * n + i], U[3 * n + i]}, f[4];
+        double u[NCMAX], f[NCMAX];
+        for (int q = 0; q < ncp; q++) u[q] = U[q * n + i];
         flux(P, d, u, f, &c);
-        for (int q = 0; q < 4; q++) F[q * n + i] = f[q];
+        for (int q = 0; q < ncp; q++) F[q * n + i] = f[q];
     }
 }
 
@@ -334,27 +387,28 @@ void ora_limiter(int32_t lim, int64_t n, const double* a, const double* b, doubl
 
 /* k stages of: centred FORCE flux from (U_L, U_R); if more stages follow,
  * the local predictor update of U_L and U_R.  lam = dt / dx_d. */
-static void musta(const ora_params* P, int d, double lam, const double UL0[4],
-                  const double UR0[4], double Fh[4], ora_counters* cnt)
+static void musta(const ora_params* P, int d, double lam, const double* UL0,
+                  const double* UR0, double* Fh, ora_counters* cnt)
 {
-    double UL[4], UR[4], FL[4], FR[4], Us[4], Flw[4], Flf[4];
+    double UL[NCMAX], UR[NCMAX], FL[NCMAX], FR[NCMAX], Us[NCMAX], Flw[NCMAX], Flf[NCMAX];
     const double alpha = P->alpha;
     const double lp = P->predictor_alpha ? alpha * lam : lam;  /* predictor coefficient */
-    for (int c = 0; c < 4; c++) { UL[c] = UL0[c]; UR[c] = UR0[c]; }
+    const int ncp = ncomp(P);
+    for (int c = 0; c < ncp; c++) { UL[c] = UL0[c]; UR[c] = UR0[c]; }
     for (int l = 1; l <= P->k; l++) {
         flux(P, d, UL, FL, cnt);
         flux(P, d, UR, FR, cnt);
         /* Lax-Wendroff (Richtmyer) flux */
-        for (int c = 0; c < 4; c++)
+        for (int c = 0; c < ncp; c++)
             Us[c] = 0.5 * (UL[c] + UR[c]) - 0.5 * alpha * lam * (FR[c] - FL[c]);
         flux(P, d, Us, Flw, cnt);
         /* Lax-Friedrichs flux */
-        for (int c = 0; c < 4; c++)
+        for (int c = 0; c < ncp; c++)
             Flf[c] = 0.5 * (FL[c] + FR[c]) - (UR[c] - UL[c]) / (2.0 * alpha * lam);
         /* FORCE = mean of the two */
-        for (int c = 0; c < 4; c++) Fh[c] = 0.5 * (Flw[c] + Flf[c]);
+        for (int c = 0; c < ncp; c++) Fh[c] = 0.5 * (Flw[c] + Flf[c]);
         if (l < P->k) {
-            for (int c = 0; c < 4; c++) {
+            for (int c = 0; c < ncp; c++) {
                 UL[c] = UL[c] - lp * (Fh[c] - FL[c]);
                 UR[c] = UR[c] - lp * (FR[c] - Fh[c]);
             }
@@ -366,12 +420,12 @@ void ora_musta(const ora_params* P, int32_t d, double lam, int64_t n, const doub
                const double* UR, double* F)
 {
     ora_counters c = {0, 0, 0, 0};
+    const int ncp = ncomp(P);
     for (int64_t i = 0; i < n; i++) {
-        double l[4] = {UL[i], UL[n + i], UL[2 * n + i], UL[3 * n + i]};
-        double r[4] = {UR[i], UR[n + i], UR[2 * n + i], UR[3 * n + i]};
-        double f[4];
+        double l[NCMAX], r[NCMAX], f[NCMAX];
+        for (int q = 0; q < ncp; q++) { l[q] = UL[q * n + i]; r[q] = UR[q * n + i]; }
         musta(P, d, lam, l, r, f, &c);
-        for (int q = 0; q < 4; q++) F[q * n + i] = f[q];
+        for (int q = 0; q < ncp; q++) F[q * n + i] = f[q];
     }
 }
 
@@ -383,16 +437,17 @@ void ora_musta(const ora_params* P, int32_t d, double lam, int64_t n, const doub
  * into out[i], i = 0..N-1.  dl: Hancock corrections of cells -1..N (dl[j] is
  * cell j-1) from the unsplit step, or NULL for the per-axis step. */
 static void line_rhs(const ora_params* P, int d, int N, double lam, double dxd,
-                     double (*u)[4], double (*uLt)[4], double (*uRt)[4], double (*F)[4],
-                     double (*out)[4], const double (*dl)[4], ora_counters* cnt)
+                     double (*u)[NCMAX], double (*uLt)[NCMAX], double (*uRt)[NCMAX], double (*F)[NCMAX],
+                     double (*out)[NCMAX], const double (*dl)[NCMAX], ora_counters* cnt)
 {
+    const int ncp = ncomp(P);
     /* MUSCL reconstruction and Hancock half step for cells -1..N */
     for (int i = -1; i <= N; i++) {
         const double* um = u[i + 1];
         const double* u0 = u[i + 2];
         const double* up = u[i + 3];
-        double UL[4], UR[4], FLc[4], FRc[4];
-        for (int c = 0; c < 4; c++) {
+        double UL[NCMAX], UR[NCMAX], FLc[NCMAX], FRc[NCMAX];
+        for (int c = 0; c < ncp; c++) {
             double a = u0[c] - um[c];
             double b = up[c] - u0[c];
             double D = limiter(P->limiter, a, b);
@@ -400,7 +455,7 @@ static void line_rhs(const ora_params* P, int d, int N, double lam, double dxd,
             UR[c] = u0[c] + 0.5 * D;
         }
         if (dl) {
-            for (int c = 0; c < 4; c++) {
+            for (int c = 0; c < ncp; c++) {
                 uLt[i + 1][c] = UL[c] + dl[i + 1][c];
                 uRt[i + 1][c] = UR[c] + dl[i + 1][c];
             }
@@ -408,7 +463,7 @@ static void line_rhs(const ora_params* P, int d, int N, double lam, double dxd,
         }
         flux(P, d, UL, FLc, cnt);
         flux(P, d, UR, FRc, cnt);
-        for (int c = 0; c < 4; c++) {
+        for (int c = 0; c < ncp; c++) {
             double delta = 0.5 * lam * (FLc[c] - FRc[c]);
             uLt[i + 1][c] = UL[c] + delta;
             uRt[i + 1][c] = UR[c] + delta;
@@ -417,7 +472,7 @@ static void line_rhs(const ora_params* P, int d, int N, double lam, double dxd,
     /* interface fluxes F_{i+1/2}, i = -1..N-1, from (Ut^R_i, Ut^L_{i+1}) */
     for (int i = -1; i <= N - 1; i++) musta(P, d, lam, uRt[i + 1], uLt[i + 2], F[i + 1], cnt);
     for (int i = 0; i < N; i++)
-        for (int c = 0; c < 4; c++) out[i][c] = -(F[i + 1][c] - F[i][c]) / dxd;
+        for (int c = 0; c < ncp; c++) out[i][c] = -(F[i + 1][c] - F[i][c]) / dxd;
 }
 
 static int64_t ghost_index(int j, int N, int bc)
@@ -438,24 +493,25 @@ static double* unsplit_corrections(const ora_params* P, const double* U, double 
     const int64_t ncell = (int64_t)nx * ny * nz;
     const int ex = nx + 2, ey = ny + 2, ez = nz + 2;
     const int64_t next = (int64_t)ex * ey * ez;
-    double* dl = malloc(sizeof(double) * 4 * (size_t)next);
+    const int ncp = ncomp(P);
+    double* dl = malloc(sizeof(double) * NCMAX * (size_t)next);
     int64_t nf = 0, nb = 0, ni = 0, nc = 0;
 #pragma omp parallel for schedule(static) reduction(+ : nf, nb, ni, nc)
     for (int64_t e = 0; e < next; e++) {
         const int i = (int)(e % ex) - 1, j = (int)((e / ex) % ey) - 1, k = (int)(e / ((int64_t)ex * ey)) - 1;
         ora_counters cnt = {0, 0, 0, 0};
-        double delta[4] = {0.0, 0.0, 0.0, 0.0};
+        double delta[NCMAX] = {0.0, 0.0, 0.0, 0.0, 0.0};
         for (int d = 0; d < 3; d++) {
-            double w[3][4];  /* cells -1, 0, +1 along d */
+            double w[3][NCMAX];  /* cells -1, 0, +1 along d */
             for (int s = -1; s <= 1; s++) {
                 int q[3] = {i, j, k};
                 q[d] += s;
                 const int64_t idx = ghost_index(q[0], nx, P->bc[0]) +
                                     nx * (ghost_index(q[1], ny, P->bc[1]) + ny * ghost_index(q[2], nz, P->bc[2]));
-                for (int c = 0; c < 4; c++) w[s + 1][c] = U[c * ncell + idx];
+                for (int c = 0; c < ncp; c++) w[s + 1][c] = U[c * ncell + idx];
             }
-            double UL[4], UR[4], FL[4], FR[4];
-            for (int c = 0; c < 4; c++) {
+            double UL[NCMAX], UR[NCMAX], FL[NCMAX], FR[NCMAX];
+            for (int c = 0; c < ncp; c++) {
                 const double D = limiter(P->limiter, w[1][c] - w[0][c], w[2][c] - w[1][c]);
                 UL[c] = w[1][c] - 0.5 * D;
                 UR[c] = w[1][c] + 0.5 * D;
@@ -463,9 +519,9 @@ static double* unsplit_corrections(const ora_params* P, const double* U, double 
             flux(P, d, UL, FL, &cnt);
             flux(P, d, UR, FR, &cnt);
             const double lam = dt / P->dx[d];
-            for (int c = 0; c < 4; c++) delta[c] = delta[c] + 0.5 * lam * (FL[c] - FR[c]);
+            for (int c = 0; c < ncp; c++) delta[c] = delta[c] + 0.5 * lam * (FL[c] - FR[c]);
         }
-        for (int c = 0; c < 4; c++) dl[4 * e + c] = delta[c];
+        for (int c = 0; c < ncp; c++) dl[NCMAX * e + c] = delta[c];
         nf += cnt.n_floor; nb += cnt.n_bad; ni += cnt.n_iter; nc += cnt.n_calls;
     }
     cnt_out->n_floor += nf; cnt_out->n_bad += nb; cnt_out->n_iter += ni; cnt_out->n_calls += nc;
@@ -479,7 +535,8 @@ static void rhs(const ora_params* P, const double* U, double t, double dt, doubl
     const int nx = P->n[0], ny = P->n[1], nz = P->n[2];
     const int64_t ncell = (int64_t)nx * ny * nz;
     const int64_t stride[3] = {1, nx, (int64_t)nx * ny};
-    memset(L, 0, sizeof(double) * 4 * (size_t)ncell);
+    const int ncp = ncomp(P);
+    memset(L, 0, sizeof(double) * (size_t)ncomp(P) * (size_t)ncell);
     int64_t nf = 0, nb = 0, ni = 0, nc = 0;
     ora_counters cpre = {0, 0, 0, 0};
     double* dl3 = P->unsplit_hancock ? unsplit_corrections(P, U, dt, &cpre) : NULL;
@@ -492,12 +549,12 @@ static void rhs(const ora_params* P, const double* U, double t, double dt, doubl
         const int64_t nlines = ncell / N;
 #pragma omp parallel reduction(+ : nf, nb, ni, nc)
         {
-            double(*u)[4] = malloc(sizeof(double[4]) * (size_t)(N + 4));
-            double(*uLt)[4] = malloc(sizeof(double[4]) * (size_t)(N + 2));
-            double(*uRt)[4] = malloc(sizeof(double[4]) * (size_t)(N + 2));
-            double(*F)[4] = malloc(sizeof(double[4]) * (size_t)(N + 1));
-            double(*out)[4] = malloc(sizeof(double[4]) * (size_t)N);
-            double(*dl)[4] = dl3 ? malloc(sizeof(double[4]) * (size_t)(N + 2)) : NULL;
+            double(*u)[NCMAX] = malloc(sizeof(double[NCMAX]) * (size_t)(N + 4));
+            double(*uLt)[NCMAX] = malloc(sizeof(double[NCMAX]) * (size_t)(N + 2));
+            double(*uRt)[NCMAX] = malloc(sizeof(double[NCMAX]) * (size_t)(N + 2));
+            double(*F)[NCMAX] = malloc(sizeof(double[NCMAX]) * (size_t)(N + 1));
+            double(*out)[NCMAX] = malloc(sizeof(double[NCMAX]) * (size_t)N);
+            double(*dl)[NCMAX] = dl3 ? malloc(sizeof(double[NCMAX]) * (size_t)(N + 2)) : NULL;
             ora_counters cnt = {0, 0, 0, 0};
 #pragma omp for schedule(static)
             for (int64_t line = 0; line < nlines; line++) {
@@ -506,17 +563,17 @@ static void rhs(const ora_params* P, const double* U, double t, double dt, doubl
                 int64_t base = i1 * stride[a1] + i2 * stride[a2];
                 for (int j = -2; j < N + 2; j++) {
                     int64_t idx = base + ghost_index(j, N, P->bc[d]) * stride[d];
-                    for (int c = 0; c < 4; c++) u[j + 2][c] = U[c * ncell + idx];
+                    for (int c = 0; c < ncp; c++) u[j + 2][c] = U[c * ncell + idx];
                 }
                 if (dl) {  /* corrections of cells -1..N along the line */
                     const int64_t ebase = (i1 + 1) * estride[a1] + (i2 + 1) * estride[a2];
                     for (int j = -1; j <= N; j++)
-                        for (int c = 0; c < 4; c++) dl[j + 1][c] = dl3[4 * (ebase + (int64_t)(j + 1) * estride[d]) + c];
+                        for (int c = 0; c < ncp; c++) dl[j + 1][c] = dl3[NCMAX * (ebase + (int64_t)(j + 1) * estride[d]) + c];
                 }
-                line_rhs(P, d, N, lam, P->dx[d], u, uLt, uRt, F, out, (const double(*)[4])dl, &cnt);
+                line_rhs(P, d, N, lam, P->dx[d], u, uLt, uRt, F, out, (const double(*)[NCMAX])dl, &cnt);
                 for (int j = 0; j < N; j++) {
                     int64_t idx = base + (int64_t)j * stride[d];
-                    for (int c = 0; c < 4; c++) L[c * ncell + idx] = L[c * ncell + idx] + out[j][c];
+                    for (int c = 0; c < ncp; c++) L[c * ncell + idx] = L[c * ncell + idx] + out[j][c];
                 }
             }
             nf += cnt.n_floor; nb += cnt.n_bad; ni += cnt.n_iter; nc += cnt.n_calls;
@@ -564,6 +621,7 @@ void ora_rhs(const ora_params* P, const double* U, double t, double dt, double* 
 double ora_max_speed(const ora_params* P, const double* U, ora_counters* cnt_out)
 {
     const int64_t ncell = (int64_t)P->n[0] * P->n[1] * P->n[2];
+    const int ncp = ncomp(P);
     double smax = 0.0;
     int64_t nf = 0, nb = 0, ni = 0, nc = 0;
 #pragma omp parallel reduction(max : smax) reduction(+ : nf, nb, ni, nc)
@@ -571,11 +629,12 @@ double ora_max_speed(const ora_params* P, const double* U, ora_counters* cnt_out
         ora_counters cnt = {0, 0, 0, 0};
 #pragma omp for schedule(static)
         for (int64_t i = 0; i < ncell; i++) {
-            double u[4] = {U[i], U[ncell + i], U[2 * ncell + i], U[3 * ncell + i]};
-            double pr[5], Mu[3], p, c2;
+            double u[NCMAX], pr[6], Mu[3], p, c2;
+            for (int q = 0; q < ncp; q++) u[q] = U[q * ncell + i];
             con2prim(P, u, pr, Mu, &cnt);
             if (P->eos == EOS_IDEAL) c2 = P->cs2;
-            else table_eval(P, pr[0], &p, &c2);
+            else if (P->eos == EOS_TABLE) table_eval(P, pr[0], &p, &c2);
+            else c2 = pr[1] > 0.0 ? P->gamma * pr[1] / (pr[0] + pr[1]) : 0.0;  /* ideal gas */
             double cs = sqrt(c2);
             double v2 = pr[2] * pr[2] + pr[3] * pr[3] + pr[4] * pr[4];
             for (int d = 0; d < 3; d++) {
@@ -598,11 +657,11 @@ double ora_max_speed(const ora_params* P, const double* U, ora_counters* cnt_out
 }
 
 /* Neumaier-compensated sums of each conserved component times the cell volume. */
-void ora_totals(const ora_params* P, const double* U, double out[4])
+void ora_totals(const ora_params* P, const double* U, double* out /* ncomp */)
 {
     const int64_t ncell = (int64_t)P->n[0] * P->n[1] * P->n[2];
     const double dV = P->dx[0] * P->dx[1] * P->dx[2];
-    for (int c = 0; c < 4; c++) {
+    for (int c = 0; c < ncomp(P); c++) {
         double s = 0.0, comp = 0.0;
         for (int64_t i = 0; i < ncell; i++) {
             double x = U[c * ncell + i];
@@ -624,12 +683,12 @@ typedef struct {
     ora_counters cnt; /* summed over all L evaluations of the call */
 } ora_stats;
 
-/* Advance U (4 x ncell, SoA, x fastest) by nsteps steps of size dt from t0. */
+/* Advance U (ncomp x ncell, SoA, x fastest) by nsteps steps of size dt from t0. */
 int ora_step(const ora_params* P, double* U, double t0, double dt, int32_t nsteps,
              ora_stats* st)
 {
     const int64_t ncell = (int64_t)P->n[0] * P->n[1] * P->n[2];
-    const int64_t nv = 4 * ncell;
+    const int64_t nv = ncomp(P) * ncell;
     double* L = malloc(sizeof(double) * (size_t)nv);
     double* U1 = malloc(sizeof(double) * (size_t)nv);
     double* U2 = (P->rk == 3) ? malloc(sizeof(double) * (size_t)nv) : NULL;

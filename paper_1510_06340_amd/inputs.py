@@ -1,10 +1,12 @@
 """Seeded synthetic inputs shared by the HIP path, the oracle and the bench.
 
-This module holds no arithmetic of the numerical method: it draws random
+This module holds none of the numerical method's steps: it draws random
 numbers, lays out grids, builds initial energy-density fields of fluid at rest
-(for v = 0 the conserved variables are E = e, M = 0, so no
-primitive-to-conserved transform is involved) and tabulates the crossover
-equation of state, whose pressure is an input to the method.
+(for v = 0 the conserved variables are E = e, M = 0), the exact Hubble-like
+state (whose conserved variables it forms from e and v by the standard
+relations E = (e + p) g^2 - p, M = (e + p) g^2 v, g^2 = 1 / (1 - v^2); a test
+checks them against the oracle's inverse) and tabulates the crossover equation
+of state, whose pressure is an input to the method.
 
 Random numbers come from SplitMix64 (Steele, Lea and Flood, "Fast splittable
 pseudorandom number generators", OOPSLA 2014) with the usual 53-bit mapping to
@@ -283,6 +285,33 @@ def crossover_workloads(n_events: int = 32, base_seed: int = 2000, n: int = 192,
                      seed=base_seed + j) for j in range(n_events)]
 
 
+def sod_workload(nx: int = 500, dx: float = 0.02, dt: float = 0.005, steps: int = 800,
+                 limiter: int = LIM_MINMOD, k: int = 4, rk: int = 3, ny: int = 1, nz: int = 1,
+                 gamma: float = 5.0 / 3.0) -> Workload:
+    """The paper's Sod shock tube (Sec. 3.2 and its parameter table): 500 cells of 0.02 along x
+    (x in [-5, 5], the jump at 0), dt = 0.005, charge n_L = 10 | n_R = 1 and pressure
+    p_L = 13 1/3 | p_R = 0 at rest, ideal gas p = (gamma - 1)(e - n) with gamma = 5/3, carried
+    with the conserved charge R; 800 steps (t = 4, where the shock is inside the box); RK3
+    and 4 MUSTA stages as in the paper's experiments; outflow in x, periodic in y, z."""
+    return Workload("sod", (nx, ny, nz), (dx, dx, dx), (-0.5 * nx * dx, -0.5 * ny * dx, -0.5 * nz * dx),
+                    (BC_OUTFLOW, BC_PERIODIC, BC_PERIODIC), limiter, k, rk, dt, steps,
+                    extra=dict(charge=True, gamma=gamma, n=(10.0, 1.0), p=(40.0 / 3.0, 0.0)))
+
+
+def sod_state(n, dx, xlo, n_lr=(10.0, 1.0), p_lr=(40.0 / 3.0, 0.0), gamma=5.0 / 3.0) -> np.ndarray:
+    """Conserved state (5, nz, ny, nx) of gas at rest with the charge and pressure jump at x = 0:
+    E = e = n + p / (gamma - 1), M = 0, R = n (v = 0)."""
+    nx, ny, nz = n
+    xs = cell_centres(nx, dx[0], xlo[0])
+    left = xs < 0.0
+    nn = np.where(left, n_lr[0], n_lr[1])
+    pp = np.where(left, p_lr[0], p_lr[1])
+    U = np.zeros((5, nz, ny, nx))
+    U[0] = np.broadcast_to(nn + pp / (gamma - 1.0), (nz, ny, nx))
+    U[4] = np.broadcast_to(nn, (nz, ny, nx))
+    return U
+
+
 def hubble_workload(n: int = 120, dx: float = 0.1, dt: float = 0.03, steps: int = 20,
                     limiter: int = LIM_MINMOD, k: int = 4, rk: int = 3) -> Workload:
     """The paper's Hubble-like expansion test (Sec. 3.2 and its parameter table): 120^3
@@ -293,9 +322,12 @@ def hubble_workload(n: int = 120, dx: float = 0.1, dt: float = 0.03, steps: int 
 
 
 def initial_state(w: Workload) -> np.ndarray:
-    """Conserved FP64 state (4, nz, ny, nx) for a workload."""
+    """Conserved FP64 state (4, nz, ny, nx) for a workload ((5, ...) with the charge R)."""
     if w.name == "shock":
         return at_rest(shock_tube_energy(w.n, w.dx, w.xlo))
+    if w.name == "sod":
+        x = w.extra
+        return sod_state(w.n, w.dx, w.xlo, x["n"], x["p"], x["gamma"])
     if w.name == "hubble":
         x = w.extra
         return hubble_state(w.n, w.dx, w.xlo, x["t0"], x["tau0"], x["e0"], w.cs2, x["edge"])
