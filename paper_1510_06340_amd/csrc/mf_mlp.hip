@@ -17,6 +17,7 @@
 //
 // Parameter block (FP32, contiguous): W1[64][2], b1[64], W2[64][64], b2[64],
 // w3[64], b3.
+#include <cmath>
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -413,8 +414,9 @@ hipError_t mlp_grad(const float* P, const float* X, const float* T, int64_t B, f
 hipError_t mlp_adam(float* P, const float* g, float* m, float* v, int step, float lr, float b1, float b2, float eps,
                     hipStream_t s)
 {
-    const float c1 = 1.0f - powf(b1, (float)step);
-    const float c2 = 1.0f - powf(b2, (float)step);
+    // bias corrections 1 - beta^step in double (1 - beta^step cancels badly in float for beta near 1)
+    const float c1 = (float)(-std::expm1((double)step * std::log1p(-(1.0 - (double)b1))));
+    const float c2 = (float)(-std::expm1((double)step * std::log1p(-(1.0 - (double)b2))));
     hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, P, g, m, v, kMlpParams, lr, b1,
                        b2, eps, c1, c2);
     return hipGetLastError();

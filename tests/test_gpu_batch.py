@@ -174,19 +174,3 @@ def test_batch_rejects_mixed_limiters():
         g.batch_step([w.dt for w in ws], 1)
     assert ei.value.code == mf.MF_ERR_ARG
     g.free()
-
-
-def test_ensemble_full_size_one_step_sampled():
-    """The 64-event ensemble at full size: one batched step; 4 events checked against the oracle."""
-    import torch
-    ws = I.ensemble_workloads()
-    Us = [I.initial_state(w) for w in ws]
-    g, dev = make_grid(ws, Us)
-    st = g.batch_step([w.dt for w in ws], 1)
-    torch.cuda.synchronize()
-    for j in (0, 17, 42, 63):
-        w = ws[j]
-        Uo, sto = oracle.step(oracle.Problem.from_workload(w), Us[j], w.dt, 1)
-        assert max_rel_err(from_dev(dev[j], Us[j].shape[1:]), Uo) <= 1e-10
-        assert st[j]["smax"] == pytest.approx(sto["smax"], rel=1e-12)
-    g.free()

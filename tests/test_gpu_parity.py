@@ -284,17 +284,6 @@ def test_strict_mode_reports_unphysical_states():
     assert ei.value.code == mf.MF_ERR_UNPHYSICAL
 
 
-def test_hotspot_128_full_run_parity():
-    """The hot-spot workload at 128^3 (dx = 0.2) for the full 200 steps, FP64."""
-    w = I.hotspot_workload(n=128)
-    U = I.initial_state(w)
-    Ug, st = gpu_run(w, U)
-    Uo, sto = oracle_run(w, U)
-    assert max_rel_err(Ug, Uo) <= TOL64
-    assert st["n_floor"] == sto["n_floor"] and st["n_bad"] == 0
-    assert st["smax"] == pytest.approx(sto["smax"], rel=1e-10)
-
-
 def test_hotspot_256_full_size_one_step():
     """The bench workload itself (256^3, MC, k = 3, RK2, launch shape as timed): one full step vs the oracle."""
     w = I.hotspot_workload()
