@@ -369,7 +369,8 @@ static double limiter(int lim, double a, double b)
         if (!same_sign(a, b)) return 0.0;
         return 2.0 * a * b / (a + b);
     case LIM_VANALBADA: /* xi = (r^2 + r) / (r^2 + 1), not clipped */
-        if (a == 0.0 && b == 0.0) return 0.0;
+        /* slopes so small that a^2 + b^2 is zero in double (|a|, |b| < 1e-154) give 0 */
+        if (a * a + b * b == 0.0) return 0.0;
         return a * b * (a + b) / (a * a + b * b);
     default:
         return 0.0;
