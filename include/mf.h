@@ -199,6 +199,22 @@ int mf_mlp_forward(const float* params, const float* X, int64_t n, float* y, voi
  * *loss (device, nullable).  work: mf_mlp_workspace(n) floats. */
 int mf_mlp_grad(const float* params, const float* X, const float* t, int64_t n, float* grad, float* loss,
                 float* work, int64_t work_floats, void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight training or serving loops, harnesses that forbid allocation): the same
+ * gradient as mf_mlp_grad, with its per-wavefront partial gradients kept in a
+ * library-owned static device array instead of a caller workspace.  The array
+ * holds the partials of up to MF_MLP_NOALLOC_MAX_N samples (4.5 MB); each GPU
+ * the library runs on holds its own copy until the process ends.  n must lie
+ * in [1, MF_MLP_NOALLOC_MAX_N] (else MF_ERR_ARG).  The call runs on the current
+ * device, and stream must belong to it.  It allocates nothing: no hipMalloc,
+ * hipFree or allocating library routine.  Every call on one GPU shares that
+ * GPU's array, and each call rewrites every partial it reads, so nothing is
+ * carried from one call to the next; calls that overlap on one GPU (two
+ * streams, or two host threads) race on the array and must be serialised by
+ * the caller.  Other arguments and errors as in mf_mlp_grad. */
+#define MF_MLP_NOALLOC_MAX_N 16384
+int mf_mlp_grad_noalloc(const float* params, const float* X, const float* t, int64_t n, float* grad, float* loss,
+                        void* stream);
 /* One Adam step (step >= 1) on params with moments m, v (MF_MLP_PARAMS each). */
 int mf_mlp_adam(float* params, const float* grad, float* m, float* v, int32_t step, float lr, float beta1,
                 float beta2, float eps, void* stream);

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -766,6 +767,39 @@ int check_desc(const mf_grid_desc& d)
 
 }  // namespace
 
+// Partial gradients of mf_mlp_grad_noalloc: one row of MF_MLP_PARAMS + 1 floats per
+// wavefront of the gradient kernel, for up to MF_MLP_NOALLOC_MAX_N samples.  Every
+// device holds its own copy; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device (the name itself is a host stand-in).
+static constexpr int64_t kNoallocFloats =
+    ((int64_t)(MF_MLP_NOALLOC_MAX_N + 255) / 256) * 4 * (MF_MLP_PARAMS + 1);
+static __device__ __align__(256) float scratch[kNoallocFloats];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+// Device address of `scratch` on the current device, looked up once per device.
+int noalloc_scratch(float** out)
+{
+    static std::mutex mu;
+    static float* ptr[kMaxDevices] = {};
+    int dev = 0;
+    MF_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(MF_ERR_ARG, "device index beyond the library's table");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        MF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(MF_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+        ptr[dev] = (float*)p;
+    }
+    *out = ptr[dev];
+    return MF_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* mf_last_error(void) { return g_err.c_str(); }
@@ -1157,6 +1191,22 @@ int mf_mlp_grad(const float* params, const float* X, const float* t, int64_t n, 
     if (work_floats < mf_mlp_workspace(n)) return fail(MF_ERR_ARG, "workspace too small (see mf_mlp_workspace)");
     hipError_t e = mlp_grad(params, X, t, n, work, grad, loss, (hipStream_t)stream);
     if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("mlp grad: ") + hipGetErrorString(e));
+    return MF_OK;
+}
+
+int mf_mlp_grad_noalloc(const float* params, const float* X, const float* t, int64_t n, float* grad, float* loss,
+                        void* stream)
+{
+    if (!params || !X || !t || !grad || n < 1) return fail(MF_ERR_ARG, "bad argument");
+    if (n > MF_MLP_NOALLOC_MAX_N)
+        return fail(MF_ERR_ARG, "n = " + std::to_string(n) + " exceeds MF_MLP_NOALLOC_MAX_N = " +
+                                    std::to_string(MF_MLP_NOALLOC_MAX_N) + " (use mf_mlp_grad with a workspace)");
+    if (mf_mlp_workspace(n) > kNoallocFloats) return fail(MF_ERR_ARG, "scratch array too small for n");
+    float* part = nullptr;
+    const int rc = noalloc_scratch(&part);
+    if (rc != MF_OK) return rc;
+    hipError_t e = mlp_grad(params, X, t, n, part, grad, loss, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("mlp grad (no-alloc): ") + hipGetErrorString(e));
     return MF_OK;
 }
 

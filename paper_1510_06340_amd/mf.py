@@ -21,13 +21,15 @@ MF_LIM_NONE, MF_LIM_MINMOD, MF_LIM_SUPERBEE, MF_LIM_MC, MF_LIM_VANLEER, MF_LIM_V
 MF_EOS_IDEAL, MF_EOS_TABLE = 0, 1
 MF_C2P_PLAIN, MF_C2P_SEEDED, MF_C2P_CONFORMAL = 0, 1, 2
 MF_MLP_HIDDEN, MF_MLP_PARAMS = 64, 4417
+MF_MLP_NOALLOC_MAX_N = 16384
 MF_FLAG_STRICT = 1
 MF_FLAG_PREDICTOR_ALPHA = 2
 MF_FLAG_UNSPLIT_HANCOCK = 4
 
 EXPORTS = ["mf_grid_init", "mf_set_eos", "mf_set_source_jet", "mf_set_time", "mf_step", "mf_batch_step",
            "mf_con2prim", "mf_con2prim_stats", "mf_totals", "mf_set_tuning", "mf_set_profiling", "mf_get_profile",
-           "mf_grid_free", "mf_last_error", "mf_mlp_workspace", "mf_mlp_forward", "mf_mlp_grad", "mf_mlp_adam"]
+           "mf_grid_free", "mf_last_error", "mf_mlp_workspace", "mf_mlp_forward", "mf_mlp_grad", "mf_mlp_grad_noalloc",
+           "mf_mlp_adam"]
 
 
 class GridDesc(C.Structure):
@@ -90,6 +92,7 @@ def lib():
         L.mf_mlp_workspace.argtypes = [C.c_int64]
         L.mf_mlp_forward.argtypes = [vp, vp, C.c_int64, vp, vp]
         L.mf_mlp_grad.argtypes = [vp, vp, vp, C.c_int64, vp, vp, vp, C.c_int64, vp]
+        L.mf_mlp_grad_noalloc.argtypes = [vp, vp, vp, C.c_int64, vp, vp, vp]
         L.mf_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, vp]
         for name in EXPORTS:
             if name not in ("mf_last_error", "mf_mlp_workspace"):
@@ -291,6 +294,14 @@ def mlp_grad(params, X, t, grad, loss, work, stream=None):
     st = stream.cuda_stream if stream is not None else None
     _check(lib().mf_mlp_grad(_ptr(params), _ptr(X), _ptr(t), X.shape[0], _ptr(grad),
                              _ptr(loss) if loss is not None else None, _ptr(work), work.numel(), st))
+
+
+def mlp_grad_noalloc(params, X, t, grad, loss, stream=None):
+    """mlp_grad with the partial gradients in the library's static device array (no workspace;
+    at most MF_MLP_NOALLOC_MAX_N samples; calls that overlap on one GPU race)."""
+    st = stream.cuda_stream if stream is not None else None
+    _check(lib().mf_mlp_grad_noalloc(_ptr(params), _ptr(X), _ptr(t), X.shape[0], _ptr(grad),
+                                     _ptr(loss) if loss is not None else None, st))
 
 
 def mlp_adam(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
