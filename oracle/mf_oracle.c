@@ -202,7 +202,8 @@ void ora_eos_eval(const ora_params* P, int64_t n, const double* e, double* p, do
  *   v = |M| / (E + p(E - |M| v, R sqrt(1 - v^2)))
  * is solved by bisection in v on [0, |M|/E] (p >= 0 puts the root there; it
  * is unique because p -> v = |M| / (E + p) maps the roots one to one onto
- * those of the decreasing function (gamma - 1)(e(p) - n(p)) - p).
+ * those of the decreasing function (gamma - 1)(e(p) - n(p)) - p).  For
+ * gamma = 1 (pressureless dust) p = 0 and v = |M|/E directly.
  * Returns the (possibly clamped) momentum used, through Mu[3];
  * prim = (e, p, vx, vy, vz, n).  Returns 0 for a state counted as bad
  * (E <= 0, a non-finite component, or R < 0 with the ideal gas), which is
@@ -265,7 +266,9 @@ static int con2prim(const ora_params* P, const double* U, double prim[6], double
         const double gm1 = P->gamma - 1.0;
         const double M = sqrt(M2);
         double v = 0.0;
-        if (M2 > 0.0) {
+        if (gm1 == 0.0) {
+            v = M / E;  /* pressureless dust: the fixed point is explicit */
+        } else if (M2 > 0.0) {
             double lo = 0.0, hi = M / E;
             int it = 0;
             while (it < 200) {  /* to the last bit: stop when the midpoint is an end */

@@ -3,9 +3,9 @@
 This module holds none of the numerical method's steps: it draws random
 numbers, lays out grids, builds initial energy-density fields of fluid at rest
 (for v = 0 the conserved variables are E = e, M = 0), the exact Hubble-like
-state (whose conserved variables it forms from e and v by the standard
-relations E = (e + p) g^2 - p, M = (e + p) g^2 v, g^2 = 1 / (1 - v^2); a test
-checks them against the oracle's inverse) and tabulates the crossover equation
+and ellipsoidal states (whose conserved variables it forms from e, n and v by
+the standard relations E = (e + p) g^2 - p, M = (e + p) g^2 v, R = n g,
+g^2 = 1 / (1 - v^2); tests check them against the oracle's inverse) and tabulates the crossover equation
 of state, whose pressure is an input to the method.
 
 Random numbers come from SplitMix64 (Steele, Lea and Flood, "Fast splittable
@@ -312,6 +312,52 @@ def sod_state(n, dx, xlo, n_lr=(10.0, 1.0), p_lr=(40.0 / 3.0, 0.0), gamma=5.0 / 
     return U
 
 
+def ellipsoidal_workload(n: int = 120, dx: float = 0.1, dt: float = 0.02, steps: int = 50,
+                         limiter: int = LIM_MINMOD, k: int = 4, rk: int = 3) -> Workload:
+    """The paper's ellipsoidal flow (Sec. 3.2 and its parameter table): 120^3 cells of 0.1
+    centred on the origin, dt = 0.02, from t0 = 2 with C_e = 2, C_n = 0.75, b_e = b_n = 1,
+    T = (0.4, 0.6, 0.8); pressureless (p = 0: the ideal gas with gamma = 1) with the charge;
+    RK3 and 4 MUSTA stages as in the paper's experiments; 50 steps (to t = 3)."""
+    return Workload("ellipsoidal", (n, n, n), (dx, dx, dx), (-0.5 * n * dx,) * 3, (BC_OUTFLOW,) * 3,
+                    limiter, k, rk, dt, steps,
+                    extra=dict(charge=True, gamma=1.0, t0=2.0, Ce=2.0, Cn=0.75, be=1.0, bn=1.0,
+                               T=(0.4, 0.6, 0.8)))
+
+
+def ellipsoidal_prim(n, dx, xlo, t, Ce=2.0, Cn=0.75, be=1.0, bn=1.0, T=(0.4, 0.6, 0.8)):
+    """Rest-frame e, n and velocity (3, ...) of the ellipsoidal flow at time t at the cell centres:
+    v_i = a_i x_i / t with a_i = t / (t + T_i), tau^2 = t^2 - sum_i (a_i x_i)^2,
+    e = C_e exp(-b_e^2 t^2 / tau^2) / prod_i (t + T_i), n likewise with C_n, b_n; outside
+    tau^2 > 0 the exponential vanishes (e = n = 0, v = 0).  (The paper prints the velocity
+    components as (a_1 x, a_3 y, a_2 z) / t; with tau built from a_i x_i the consistent reading
+    is a_i x_i / t for every axis.)"""
+    nx, ny, nz = n
+    xs = [cell_centres(nx, dx[0], xlo[0])[None, None, :], cell_centres(ny, dx[1], xlo[1])[None, :, None],
+          cell_centres(nz, dx[2], xlo[2])[:, None, None]]
+    a = [t / (t + Ti) for Ti in T]
+    v = [np.broadcast_to(a[i] * xs[i] / t, (nz, ny, nx)) for i in range(3)]
+    tau2 = t * t - t * t * (v[0] ** 2 + v[1] ** 2 + v[2] ** 2)
+    inside = tau2 > 0.0
+    ratio = np.where(inside, t * t / np.where(inside, tau2, 1.0), np.inf)
+    den = (t + T[0]) * (t + T[1]) * (t + T[2])
+    e = Ce / den * np.exp(-be * be * ratio)
+    nn = Cn / den * np.exp(-bn * bn * ratio)
+    vv = np.stack([np.where(inside, vi, 0.0) for vi in v])
+    return e, nn, vv
+
+
+def ellipsoidal_state(n, dx, xlo, t, **kw) -> np.ndarray:
+    """Conserved state (5, nz, ny, nx) of the ellipsoidal flow at time t (p = 0):
+    E = e W^2, M = e W^2 v, R = n W."""
+    e, nn, v = ellipsoidal_prim(n, dx, xlo, t, **kw)
+    W2 = 1.0 / (1.0 - (v ** 2).sum(0))
+    U = np.empty((5,) + e.shape)
+    U[0] = e * W2
+    U[1:4] = (e * W2)[None] * v
+    U[4] = nn * np.sqrt(W2)
+    return U
+
+
 def hubble_workload(n: int = 120, dx: float = 0.1, dt: float = 0.03, steps: int = 20,
                     limiter: int = LIM_MINMOD, k: int = 4, rk: int = 3) -> Workload:
     """The paper's Hubble-like expansion test (Sec. 3.2 and its parameter table): 120^3
@@ -328,6 +374,9 @@ def initial_state(w: Workload) -> np.ndarray:
     if w.name == "sod":
         x = w.extra
         return sod_state(w.n, w.dx, w.xlo, x["n"], x["p"], x["gamma"])
+    if w.name == "ellipsoidal":
+        x = w.extra
+        return ellipsoidal_state(w.n, w.dx, w.xlo, x["t0"], Ce=x["Ce"], Cn=x["Cn"], be=x["be"], bn=x["bn"], T=x["T"])
     if w.name == "hubble":
         x = w.extra
         return hubble_state(w.n, w.dx, w.xlo, x["t0"], x["tau0"], x["e0"], w.cs2, x["edge"])

@@ -240,3 +240,33 @@ def test_max_speed_ideal_gas():
     E, M, R = prim_to_cons(2.0, 0.0, v, G)
     U[0], U[1], U[4] = E, M, R
     assert oracle.max_speed(prob, U) == pytest.approx(v, rel=1e-12)
+
+
+def test_ellipsoidal_flow_converges_to_exact_solution():
+    """The paper's ellipsoidal flow (Sec. 3.2; pressureless dust with the charge, gamma = 1) from
+    the exact state at t0 = 2 to t = 2.4 on [-2, 2]^3: in the central region r < 1 the oracle
+    follows the exact e, n and v, and the error falls with resolution.  The state is formed
+    from (e, n, v) and the oracle's con2prim returns them where there is matter."""
+    errs = []
+    for N in (24, 48):
+        dx = 4.0 / N
+        dt = 0.2 * dx
+        steps = int(round(0.4 / dt))
+        w = I.ellipsoidal_workload(n=N, dx=dx, dt=dt, steps=steps)
+        U = I.initial_state(w)
+        prob = oracle.Problem.from_workload(w)
+        p0, _ = oracle.con2prim(prob, U)
+        e0, n0, v0 = I.ellipsoidal_prim(w.n, w.dx, w.xlo, 2.0)
+        m = U[0] > 0
+        assert np.abs(p0[0][m] - e0[m]).max() <= 1e-13 * e0.max() and np.all(p0[1] == 0.0)
+        assert np.abs(p0[5][m] - n0[m]).max() <= 1e-13 * n0.max()
+        V, st = oracle.step(prob, U, dt, steps, 2.0)
+        prim, _ = oracle.con2prim(prob, V)
+        e, nn, v = I.ellipsoidal_prim(w.n, w.dx, w.xlo, 2.0 + steps * dt)
+        x = I.cell_centres(N, dx, w.xlo[0])
+        c = np.sqrt(x[None, None, :] ** 2 + x[None, :, None] ** 2 + x[:, None, None] ** 2) < 1.0
+        errs.append((np.abs(prim[0][c] - e[c]).max() / e[c].max(), np.abs(prim[5][c] - nn[c]).max() / nn[c].max(),
+                     np.abs(prim[2:5][:, c] - v[:, c]).max()))
+    (e1, n1, v1), (e2, n2, v2) = errs
+    assert e1 < 6e-3 and n1 < 6e-3 and v1 < 3e-3, errs
+    assert e1 / e2 > 1.4 and n1 / n2 > 1.3 and v1 / v2 > 1.4, errs
