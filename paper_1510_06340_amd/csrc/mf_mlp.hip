@@ -2,9 +2,13 @@
 // gfx950 with bfloat16 weights and FP32 accumulation.
 //
 // The 64 x 64 hidden layer runs on the matrix cores
-// (v_mfma_f32_16x16x16_bf16: A 16x16 (M x K), B 16x16 (K x N), each lane
-// holding 4 consecutive K values; lane l holds A[l % 16][4 (l / 16) + i] and
-// B[4 (l / 16) + i][l % 16]; the accumulator holds D[4 (l / 16) + i][l % 16]).
+// (gfx950's v_mfma_f32_16x16x32_bf16: A 16x32 (M x K), B 32x16 (K x N), each
+// lane holding 8 K values; lane l holds A[l % 16][8 (l / 16) + i] and
+// B[8 (l / 16) + i][l % 16], i = 0..7; the accumulator holds
+// D[4 (l / 16) + i][l % 16], i = 0..3).  Only the K values a lane holds must
+// agree between A and B, so a product over samples may take its K slots in
+// any order (the weight gradient uses that to feed the accumulator layout of
+// the forward pass straight back in as its A operand).
 // One wavefront owns 64 samples (4 M-tiles); layers 1 and 3 (K = 2, N = 1)
 // run on the vector ALUs.
 //
@@ -28,6 +32,8 @@
 namespace mf {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int H = kMlpHidden;
@@ -39,7 +45,7 @@ constexpr int OFF_W3 = OFF_B2 + H;
 constexpr int OFF_B3 = OFF_W3 + H;
 static_assert(OFF_B3 + 1 == kMlpParams, "parameter layout");
 
-constexpr int LDA = H + 4;  // padded LDS row (bf16 elements)
+constexpr int LDA = H + 8;  // padded LDS row (bf16 elements; 16-byte aligned rows for the 8-value reads)
 
 __device__ __forceinline__ unsigned short f2bf(float f)
 {
@@ -52,8 +58,17 @@ __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float
 
 __device__ __forceinline__ float bfr(float f) { return bf2f(f2bf(f)); }
 
-// Shared-memory image of the weights used by the matrix-core layer.
-struct MlpShared {
+// Eight bf16 values from LDS (16-byte aligned) as a matrix-core operand.
+__device__ __forceinline__ bf16x8 lds8(const unsigned short* p) { return __builtin_bit_cast(bf16x8, *(const s16x8*)p); }
+
+__device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Shared-memory image of the weights used by the matrix-core layer (16-byte
+// aligned rows: the matrix operands are read 8 values at a time).
+struct __align__(16) MlpShared {
     unsigned short w2[H * LDA];   // bf(W2)[n][k]
     unsigned short w2t[H * LDA];  // bf(W2)[k][n] (transposed)
     float w1[2 * H];              // bf(W1)
@@ -100,12 +115,10 @@ __device__ __forceinline__ void mlp_forward_wave(const MlpShared& s, unsigned sh
     const int r = l & 15, q = l >> 4;
     for (int mt = 0; mt < 4; mt++) {
         for (int nt = 0; nt < 4; nt++) acc[mt][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        for (int kt = 0; kt < 4; kt++) {
-            const bf16x4 a = *(const bf16x4*)&sA[(mt * 16 + r) * LDA + kt * 16 + 4 * q];
-            for (int nt = 0; nt < 4; nt++) {
-                const bf16x4 b = *(const bf16x4*)&s.w2[(nt * 16 + r) * LDA + kt * 16 + 4 * q];
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[mt][nt], 0, 0, 0);
-            }
+        for (int kt = 0; kt < 2; kt++) {
+            const bf16x8 a = lds8(&sA[(mt * 16 + r) * LDA + kt * 32 + 8 * q]);
+            for (int nt = 0; nt < 4; nt++)
+                acc[mt][nt] = mfma32(a, lds8(&s.w2[(nt * 16 + r) * LDA + kt * 32 + 8 * q]), acc[mt][nt]);
         }
     }
     // layer 3 (VALU): y[s] = sum_n bf(w3)[n] tanh(z2[s][n] + b2[n]) + b3
@@ -128,7 +141,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ P
                                                      int64_t B, float* __restrict__ y)
 {
     __shared__ MlpShared s;
-    __shared__ unsigned short sA[4][64 * LDA];
+    __shared__ __align__(16) unsigned short sA[4][64 * LDA];
     load_shared(P, s);
     __syncthreads();
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -156,8 +169,8 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ P, c
                                                   const float* __restrict__ T, int64_t B, float* __restrict__ part)
 {
     __shared__ MlpShared s;
-    __shared__ unsigned short sA[4][64 * LDA];   // h1b per wavefront
-    __shared__ unsigned short sD[4][64 * LDA];   // dz2b per wavefront ([s][n])
+    __shared__ __align__(16) unsigned short sA[4][64 * LDA];   // h1b per wavefront
+    __shared__ __align__(16) unsigned short sD[4][64 * LDA];   // dz2b per wavefront ([s][n])
     __shared__ float sX[4][64][2];
     load_shared(P, s);
     __syncthreads();
@@ -205,15 +218,20 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ P, c
     __syncthreads();
 
     float* out = part + ((int64_t)blockIdx.x * 4 + w) * (kMlpParams + 1);
-    // dW2[n][k] = sum_s dz2b[s][n] h1b[s][k]: A = dz2b^T (held in registers), B[s][k] = h1b from sA
+    // dW2[n][k] = sum_s dz2b[s][n] h1b[s][k]: A = dz2b^T, B[s][k] = h1b from sA.  One matrix
+    // instruction sums 32 samples, two row tiles mt = 2t, 2t + 1: the lane's 8 K slots are
+    // samples 16 mt + 4 q + i (i = 0..3) of both tiles, which is exactly what it holds of
+    // dz2b in the accumulator layout, so A is two register tiles side by side.
     for (int nt = 0; nt < 4; nt++)
         for (int kt = 0; kt < 4; kt++) {
             f32x4 g = {0.0f, 0.0f, 0.0f, 0.0f};
-            for (int mt = 0; mt < 4; mt++) {
-                short v[4];
-                for (int i = 0; i < 4; i++) v[i] = (short)sA[w][(mt * 16 + 4 * q + i) * LDA + kt * 16 + r];
-                const bf16x4 b = bf16x4{v[0], v[1], v[2], v[3]};
-                g = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(dzA[mt][nt], b, g, 0, 0, 0);
+            for (int t = 0; t < 2; t++) {
+                short v[8];
+                for (int i = 0; i < 8; i++)
+                    v[i] = (short)sA[w][((2 * t + i / 4) * 16 + 4 * q + i % 4) * LDA + kt * 16 + r];
+                const s16x8 bv = s16x8{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]};
+                const s16x8 av = __builtin_shufflevector(dzA[2 * t][nt], dzA[2 * t + 1][nt], 0, 1, 2, 3, 4, 5, 6, 7);
+                g = mfma32(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv), g);
             }
             for (int i = 0; i < 4; i++) out[OFF_W2 + (nt * 16 + 4 * q + i) * H + kt * 16 + r] = g[i];
         }
@@ -222,11 +240,9 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ P, c
     for (int mt = 0; mt < 4; mt++)
         for (int kt = 0; kt < 4; kt++) {
             f32x4 g = {0.0f, 0.0f, 0.0f, 0.0f};
-            for (int nt = 0; nt < 4; nt++) {
-                const bf16x4 a = *(const bf16x4*)&sD[w][(mt * 16 + r) * LDA + nt * 16 + 4 * q];
-                const bf16x4 b = *(const bf16x4*)&s.w2t[(kt * 16 + r) * LDA + nt * 16 + 4 * q];
-                g = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, g, 0, 0, 0);
-            }
+            for (int nk = 0; nk < 2; nk++)
+                g = mfma32(lds8(&sD[w][(mt * 16 + r) * LDA + nk * 32 + 8 * q]),
+                           lds8(&s.w2t[(kt * 16 + r) * LDA + nk * 32 + 8 * q]), g);
             // dz1 = dh1 (1 - h1^2), with h1 recomputed from the sample's x (padding samples have dz2 = 0)
             const int k = kt * 16 + r;
             for (int i = 0; i < 4; i++) {
@@ -311,7 +327,7 @@ __global__ __launch_bounds__(256) void k_con2prim_seeded(C2PArgs<double> a, EosT
                                                          SeedNorm nrm, int mode)
 {
     __shared__ MlpShared s;
-    __shared__ unsigned short sA[4][64 * LDA];
+    __shared__ __align__(16) unsigned short sA[4][64 * LDA];
     __shared__ float sy[4][64];
     if (mode == 1) load_shared(P, s);
     __syncthreads();
