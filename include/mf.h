@@ -55,7 +55,12 @@ enum mf_limiter {
     MF_LIM_VANLEER = 4,   /* xi(r) = (r + |r|) / (1 + |r|) */
     MF_LIM_VANALBADA = 5  /* xi(r) = (r^2 + r) / (r^2 + 1) */
 };
-enum mf_eos_kind { MF_EOS_IDEAL = 0, MF_EOS_TABLE = 1 };
+enum mf_eos_kind {
+    MF_EOS_IDEAL = 0,  /* p = cs2 e */
+    MF_EOS_TABLE = 1,  /* tabulated p(e), monotone cubic */
+    MF_EOS_GAMMA = 2   /* ideal gas p = (gamma - 1) max(e - n, 0), n the rest-frame charge
+                          density (needs MF_FLAG_CHARGE) */
+};
 enum mf_c2p_mode {
     MF_C2P_PLAIN = 0,     /* bracketed Newton from the bracket midpoint (table) / closed form (ideal) */
     MF_C2P_SEEDED = 1,    /* table EoS: guess from the learned seed network, evaluated on the matrix cores */
@@ -73,6 +78,13 @@ enum mf_c2p_mode {
                                        sweep's own axis term.  mf_step only (mf_batch_step
                                        returns MF_ERR_ARG); the library allocates
                                        4 (n0+2)(n1+2)(n2+2) elements per event for it */
+
+#define MF_FLAG_CHARGE 8u  /* a fifth conserved component, the charge R = n gamma of Sec. 2.1
+                              (flux R v_d; n = R sqrt(1 - v^2), Sec. 2.6): U_dev holds 5
+                              pointers per event (E, Mx, My, Mz, R).  All events of a handle
+                              carry it or none does; FP64 only; with MF_EOS_IDEAL (a passive
+                              charge) or MF_EOS_GAMMA, through mf_step (not mf_batch_step,
+                              the jet source or MF_FLAG_UNSPLIT_HANCOCK: MF_ERR_ARG) */
 
 typedef struct mf_grid_s* mf_grid_t;
 
@@ -130,20 +142,26 @@ typedef struct {
 
 /* Create a handle for n_events independent grids (Sec. 2.1 problem statement,
  * one descriptor per event).  U_dev holds 4 device pointers per event
- * (E, Mx, My, Mz, each n[0]*n[1]*n[2] elements of the event's dtype).
+ * (E, Mx, My, Mz, each n[0]*n[1]*n[2] elements of the event's dtype), or 5
+ * (E, Mx, My, Mz, R) with MF_FLAG_CHARGE.
  * stream: hipStream_t or NULL.  Errors: MF_ERR_ARG (n < 1, dx <= 0, k < 1,
  * rk not 2/3, alpha <= 0, unknown codes, NULL pointers), MF_ERR_NOMEM, MF_ERR_HIP. */
 int mf_grid_init(mf_grid_t* out, const mf_grid_desc* descs, int32_t n_events,
                  void* const* U_dev, void* stream);
 
-/* Equation of state p(e) (Sec. 2.1, closure p = p(e, n) without charge).
+/* Equation of state (Sec. 2.1, closure p = p(e, n)).
  * MF_EOS_IDEAL: p = cs2 * e with 0 < cs2 < 1; the table arguments are ignored.
+ * MF_EOS_GAMMA: the ideal gas p = (gamma - 1) max(e - n, 0) with the adiabatic
+ * index gamma in [1, 2] passed as cs2 (gamma = 1: pressureless dust); needs
+ * MF_FLAG_CHARGE.  con2prim solves the fixed point of Sec. 2.6 for p by
+ * safeguarded Newton; cold gas (p = 0) is exact.
  * MF_EOS_TABLE: n_tab >= 2 host nodes (e_tab strictly increasing, > 0;
  * p_tab non-decreasing, >= 0, p < e) interpolated by a monotone piecewise
  * cubic; below e_tab[0] p = p_tab[0] e / e_tab[0], above the last node linear
  * with the end slope.  Fast interval lookup assumes log-uniform nodes and
  * falls back to bisection otherwise.  s (nullable) attaches the learned seed.
- * Host arrays are copied.  Errors: MF_ERR_ARG. */
+ * Host arrays are copied.  Errors: MF_ERR_ARG (also MF_EOS_TABLE with the
+ * charge, MF_EOS_GAMMA without it). */
 int mf_set_eos(mf_grid_t g, int32_t kind, double cs2, const double* e_tab,
                const double* p_tab, int32_t n_tab, const mf_surrogate* s);
 
@@ -173,11 +191,12 @@ int mf_batch_step(mf_grid_t g, const double* dt, int32_t nsteps, mf_stats* st);
 
 /* Conserved -> primitive recovery (Sec. 2.6) of n states with the handle's
  * EoS and dtype: U = 4 device arrays (E, Mx, My, Mz), prim = 5 device arrays
- * (e, p, vx, vy, vz).  iters_dev (nullable, int32 device array of n) receives
+ * (e, p, vx, vy, vz); with MF_FLAG_CHARGE U = 5 (R last) and prim = 6 (the
+ * rest-frame charge density n = R sqrt(1 - v^2) last).  iters_dev (nullable, int32 device array of n) receives
  * the root-finder iterations per state (0 for the closed form).  mode:
  * MF_C2P_PLAIN (midpoint start, whether or not a seed is installed),
  * MF_C2P_SEEDED (needs a surrogate) or MF_C2P_CONFORMAL.  Asynchronous. */
-int mf_con2prim(mf_grid_t g, const void* const U[4], void* const prim[5], int64_t n,
+int mf_con2prim(mf_grid_t g, const void* const U[], void* const prim[], int64_t n,
                 int32_t* iters_dev, int32_t mode);
 
 /* Counters of the last mf_con2prim call: out = (clamped |M|, bad states,
@@ -219,9 +238,10 @@ int mf_mlp_grad_noalloc(const float* params, const float* X, const float* t, int
 int mf_mlp_adam(float* params, const float* grad, float* m, float* v, int32_t step, float lr, float beta1,
                 float beta2, float eps, void* stream);
 
-/* Sums of (E, Mx, My, Mz) * dV over one event's cells (deterministic order).
+/* Sums of (E, Mx, My, Mz) * dV over one event's cells (deterministic order),
+ * and of R * dV as out[4] with MF_FLAG_CHARGE (out then holds 5 doubles).
  * Synchronous. */
-int mf_totals(mf_grid_t g, int32_t event, double out[4]);
+int mf_totals(mf_grid_t g, int32_t event, double* out);
 
 /* Per-step kernel shape (0 = automatic): seg[0] = chunks of 64 row items per
  * wavefront of the x sweep, seg[1], seg[2] = cells per thread along y and z;

@@ -46,6 +46,15 @@ template <> struct Math<double> {
     }
     // sqrt that also returns 0 for x == 0 (rsq(0) is +inf).
     static __device__ __forceinline__ double sqrt0(double x) { return x > 0.0 ? sqrt(x) : 0.0; }
+    // sqrt for any x >= 0: below 2^-767 (where the hardware estimate does not hold, e.g. the
+    // squared momenta of near-vacuum states) the argument is scaled by 2^256 and the result
+    // by 2^-128, which is exact.  For the guards' slow paths, not the common path.
+    static __device__ __forceinline__ double sqrt_safe(double x)
+    {
+        const bool tiny = x < 0x1p-767;
+        const double r = sqrt0(tiny ? x * 0x1p+256 : x);
+        return tiny ? r * 0x1p-128 : r;
+    }
     static __device__ __forceinline__ double div(double a, double b) { return a / b; }
 };
 
@@ -53,6 +62,7 @@ template <> struct Math<float> {
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
     static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float sqrt0(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float sqrt_safe(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 };
 
@@ -70,6 +80,24 @@ __device__ __forceinline__ bool lane_in(uint64_t mask)
 template <typename T> __device__ __forceinline__ T big_value();
 template <> __device__ __forceinline__ double big_value<double>() { return 1.79769313486231570e308; }
 template <> __device__ __forceinline__ float big_value<float>() { return 3.40282347e38f; }
+
+// Near-vacuum states: below tiny_value the square E^2 (and |M|^2) leaves the
+// range where the hardware reciprocal and square-root estimates hold, so such
+// states are evaluated scaled up by an exact power of two (up_scale) and their
+// fluxes and energies scaled back (down_scale).  con2prim of p = c e and of the
+// ideal gas is invariant under that scaling (v is unchanged, e, n, p and the
+// fluxes scale with the state); a table EoS is linear there (far below its
+// first node).  Chosen so that every positive double below tiny_value lands,
+// with its square, in the normal range above 2^-767.
+template <typename T> __device__ __forceinline__ T tiny_value();
+template <> __device__ __forceinline__ double tiny_value<double>() { return 0x1p-380; }
+template <> __device__ __forceinline__ float tiny_value<float>() { return 0x1p-60f; }
+template <typename T> __device__ __forceinline__ T up_scale();
+template <> __device__ __forceinline__ double up_scale<double>() { return 0x1p+700; }
+template <> __device__ __forceinline__ float up_scale<float>() { return 0x1p+100f; }
+template <typename T> __device__ __forceinline__ T down_scale();
+template <> __device__ __forceinline__ double down_scale<double>() { return 0x1p-700; }
+template <> __device__ __forceinline__ float down_scale<float>() { return 0x1p-100f; }
 
 // Largest admitted |M| / E; larger momenta are scaled down to it for the
 // evaluation (the stored state is not changed).
@@ -89,7 +117,8 @@ struct Counts {
 
 // ---------------------------------------------------------------------------
 // Equations of state.  An EoS provides
-//   flux<D>(U, F, counts):  F = F_D(U) after con2prim,
+//   flux<D, NC>(U, F, counts):  F = F_D(U) after con2prim, for NC = 4
+//       components (E, Mx, My, Mz) or 5 (with the charge R, flux R v_D);
 //   prim(U, e, p, v[3], cs2, counts): full primitive recovery.
 // ---------------------------------------------------------------------------
 
@@ -132,7 +161,7 @@ template <typename T> struct EosIdeal {
         }
         const T Mlim = mmax<T>() * E;
         if (M2 > Mlim * Mlim) {
-            const T s = Math<T>::div(Mlim, Math<T>::sqrt(M2));
+            const T s = Math<T>::div(Mlim, Math<T>::sqrt_safe(M2));
             Mx = Mx * s; My = My * s; Mz = Mz * s;
             M2 = Mx * Mx + My * My + Mz * Mz;
             cnt.floor_ += cnt.w;
@@ -140,9 +169,9 @@ template <typename T> struct EosIdeal {
         return true;
     }
 
-    // The energy flux (E + p) v_D is M_D: r = 1 / (E + p) at the root.
+    // The energy flux (E + p) v_D is M_D: r = 1 / (E + p) at the root.  Returns v_D.
     template <int D>
-    __device__ __forceinline__ void flux_core(T E, T Mx, T My, T Mz, T M2, T F[4]) const
+    __device__ __forceinline__ T flux_core(T E, T Mx, T My, T Mz, T M2, T F[4]) const
     {
         const T r = inv_half_den(E, E * E, M2);   // v_vec = r M
         const T e = E - r * M2;                   // E - M.v
@@ -154,43 +183,66 @@ template <typename T> struct EosIdeal {
         F[2] = My * vD;
         F[3] = Mz * vD;
         F[1 + D] = F[1 + D] + p;
+        return vD;
     }
 
     // F = F_D(U) after con2prim.  The common path has no guard branches; when
     // any lane of the wavefront holds a state that needs a guard, those lanes
-    // are re-evaluated on the slow path.
-    template <int D>
-    __device__ __forceinline__ void flux(const T u[4], T F[4], Counts& cnt) const
+    // are re-evaluated on the slow path.  With the charge (NC = 5) p does not
+    // depend on n, and the charge flux is R v_D.
+    template <int D, int NC = 4>
+    __device__ __forceinline__ void flux(const T u[], T F[], Counts& cnt) const
     {
         const T E = u[0], Mx = u[1], My = u[2], Mz = u[3];
         const T M2 = Mx * Mx + My * My + Mz * Mz;
         const T Mlim = mmax<T>() * E;
-        const uint64_t bad = lanes_where(!(E > T(0))) | lanes_where(!(E <= big_value<T>())) |
-                             lanes_where(!(M2 <= Mlim * Mlim));
-        flux_core<D>(E, Mx, My, Mz, M2, F);
+        // the first compare also sends near-vacuum states (E below tiny_value) to the slow path
+        uint64_t bad = lanes_where(!(E >= tiny_value<T>())) | lanes_where(!(E <= big_value<T>())) |
+                       lanes_where(!(M2 <= Mlim * Mlim));
+        if constexpr (NC == 5) bad |= lanes_where(!(fabs(u[4]) <= big_value<T>()));
+        const T vD = flux_core<D>(E, Mx, My, Mz, M2, F);
+        if constexpr (NC == 5) F[4] = u[4] * vD;
         if (bad != 0) {
             if (lane_in(bad)) {
-                T Ef = E, mx = Mx, my = My, mz = Mz, m2 = M2;
-                if (fixup(Ef, mx, my, mz, m2, cnt)) {
-                    flux_core<D>(Ef, mx, my, mz, m2, F);
+                const bool small = (E > T(0)) & (E < tiny_value<T>());
+                const T sc = small ? up_scale<T>() : T(1);
+                T Ef = E * sc, mx = Mx * sc, my = My * sc, mz = Mz * sc;
+                T m2 = mx * mx + my * my + mz * mz;
+                bool live = fixup(Ef, mx, my, mz, m2, cnt);
+                if constexpr (NC == 5) {
+                    if (live && !(fabs(u[4]) <= big_value<T>())) {
+                        cnt.bad += cnt.w;
+                        live = false;
+                    }
+                }
+                if (live) {
+                    const T vf = flux_core<D>(Ef, mx, my, mz, m2, F);
+                    if (small) {
+#pragma unroll
+                        for (int c = 0; c < 4; c++) F[c] = F[c] * down_scale<T>();
+                    }
+                    if constexpr (NC == 5) F[4] = u[4] * vf;
                 } else {
-                    F[0] = T(0); F[1] = T(0); F[2] = T(0); F[3] = T(0);
+#pragma unroll
+                    for (int c = 0; c < NC; c++) F[c] = T(0);
                 }
             }
         }
     }
 
     // Fluxes of two independent states.
-    template <int D>
-    __device__ __forceinline__ void flux2(const T uA[4], const T uB[4], T FA[4], T FB[4], Counts& cnt) const
+    template <int D, int NC = 4>
+    __device__ __forceinline__ void flux2(const T uA[], const T uB[], T FA[], T FB[], Counts& cnt) const
     {
-        flux<D>(uA, FA, cnt);
-        flux<D>(uB, FB, cnt);
+        flux<D, NC>(uA, FA, cnt);
+        flux<D, NC>(uB, FB, cnt);
     }
 
-    __device__ __forceinline__ void prim(const T u[4], T& e, T& p, T v[3], T& cs2, Counts& cnt) const
+    __device__ __forceinline__ void prim(const T u[], T& e, T& p, T v[3], T& cs2, Counts& cnt) const
     {
-        T E = u[0], Mx = u[1], My = u[2], Mz = u[3];
+        const bool small = (u[0] > T(0)) & (u[0] < tiny_value<T>());
+        const T sc = small ? up_scale<T>() : T(1);
+        T E = u[0] * sc, Mx = u[1] * sc, My = u[2] * sc, Mz = u[3] * sc;
         T M2 = Mx * Mx + My * My + Mz * Mz;
         cs2 = c;
         if (!fixup(E, Mx, My, Mz, M2, cnt)) {
@@ -200,6 +252,7 @@ template <typename T> struct EosIdeal {
         const T r = inv_half_den(E, E * E, M2);
         v[0] = r * Mx; v[1] = r * My; v[2] = r * Mz;
         e = E - (Mx * v[0] + My * v[1] + Mz * v[2]);
+        if (small) e = e * down_scale<T>();
         p = c * e;
     }
 };
@@ -454,7 +507,7 @@ struct EosTable {
         }
         const double Mlim = mmax<double>() * E;
         if (M2 > Mlim * Mlim) {
-            const double s = Mlim / Math<double>::sqrt(M2);
+            const double s = Mlim / Math<double>::sqrt_safe(M2);
             Mx = Mx * s; My = My * s; Mz = Mz * s;
             M2 = Mx * Mx + My * My + Mz * Mz;
             cnt.floor_ += cnt.w;
@@ -465,15 +518,26 @@ struct EosTable {
     // Guards for every lane of the wavefront at once: states that need one
     // are fixed (or replaced by a harmless state at rest and flagged) inside a
     // wave-uniform branch, so the solve below runs once for all lanes.
+    // Near-vacuum states (E below tiny_value) are scaled up by up_scale (the
+    // table is linear there, so con2prim is invariant): their lanes are
+    // returned in *scaled, whose fluxes the caller scales back.
     __device__ __forceinline__ bool guard(double& E, double& Mx, double& My, double& Mz, double& M2,
-                                          Counts& cnt) const
+                                          Counts& cnt, uint64_t& scaled) const
     {
         const double Mlim = mmax<double>() * E;
-        const uint64_t bad = lanes_where(!(E > 0.0)) | lanes_where(!(E <= big_value<double>())) |
+        const uint64_t bad = lanes_where(!(E >= tiny_value<double>())) | lanes_where(!(E <= big_value<double>())) |
                              lanes_where(!(M2 <= Mlim * Mlim));
         bool live = true;
+        scaled = 0;
         if (bad != 0) {
+            const bool small = (E > 0.0) & (E < tiny_value<double>());
+            scaled = lanes_where(small);
             if (lane_in(bad)) {
+                if (small) {
+                    E = E * up_scale<double>(); Mx = Mx * up_scale<double>();
+                    My = My * up_scale<double>(); Mz = Mz * up_scale<double>();
+                    M2 = Mx * Mx + My * My + Mz * Mz;
+                }
                 live = fixup(E, Mx, My, Mz, M2, cnt);
                 if (!live) {
                     E = 1.0; Mx = 0.0; My = 0.0; Mz = 0.0; M2 = 0.0;
@@ -481,6 +545,17 @@ struct EosTable {
             }
         }
         return live;
+    }
+
+    // Fluxes of the scaled lanes back to the state's scale.
+    __device__ __forceinline__ static void unscale(uint64_t scaled, double F[4])
+    {
+        if (scaled != 0) {
+            if (lane_in(scaled)) {
+#pragma unroll
+                for (int c = 0; c < 4; c++) F[c] = F[c] * down_scale<double>();
+            }
+        }
     }
 
     // Flux from the recovered pressure.
@@ -498,30 +573,35 @@ struct EosTable {
         F[1 + D] = live ? F[1 + D] + p : 0.0;
     }
 
-    template <int D>
-    __device__ __forceinline__ void flux(const double u[4], double F[4], Counts& cnt) const
+    template <int D, int NC = 4>
+    __device__ __forceinline__ void flux(const double u[], double F[], Counts& cnt) const
     {
+        static_assert(NC == 4, "the tabulated EoS carries no charge");
         double E = u[0], Mx = u[1], My = u[2], Mz = u[3];
         double M2 = Mx * Mx + My * My + Mz * Mz;
-        const bool live = guard(E, Mx, My, Mz, M2, cnt);
+        uint64_t scaled;
+        const bool live = guard(E, Mx, My, Mz, M2, cnt, scaled);
         double p, dp;
         recover(E, M2, p, dp, cnt);
         assemble<D>(E, Mx, My, Mz, p, live, F);
+        unscale(scaled, F);
     }
 
     // Fluxes of two independent states, computed as flux() does but with the
     // first table lookups of both issued together (eval2): in the sweeps the
     // lookups are L2 hits whose latency would otherwise be paid twice.
-    template <int D>
-    __device__ __forceinline__ void flux2(const double uA[4], const double uB[4], double FA[4], double FB[4],
+    template <int D, int NC = 4>
+    __device__ __forceinline__ void flux2(const double uA[], const double uB[], double FA[], double FB[],
                                           Counts& cnt) const
     {
+        static_assert(NC == 4, "the tabulated EoS carries no charge");
         double EA = uA[0], MxA = uA[1], MyA = uA[2], MzA = uA[3];
         double EB = uB[0], MxB = uB[1], MyB = uB[2], MzB = uB[3];
         double M2A = MxA * MxA + MyA * MyA + MzA * MzA;
         double M2B = MxB * MxB + MyB * MyB + MzB * MzB;
-        const bool liveA = guard(EA, MxA, MyA, MzA, M2A, cnt);
-        const bool liveB = guard(EB, MxB, MyB, MzB, M2B, cnt);
+        uint64_t scA, scB;
+        const bool liveA = guard(EA, MxA, MyA, MzA, M2A, cnt, scA);
+        const bool liveB = guard(EB, MxB, MyB, MzB, M2B, cnt, scB);
         double loA, eA, loB, eB;
         start(EA, M2A, loA, eA, cnt);
         start(EB, M2B, loB, eB, cnt);
@@ -531,12 +611,16 @@ struct EosTable {
         newton(EB, M2B, loB, eB, pB, dpB, cnt);
         assemble<D>(EA, MxA, MyA, MzA, pA, liveA, FA);
         assemble<D>(EB, MxB, MyB, MzB, pB, liveB, FB);
+        unscale(scA, FA);
+        unscale(scB, FB);
     }
 
-    __device__ __forceinline__ void prim(const double u[4], double& e, double& p, double v[3], double& cs2,
+    __device__ __forceinline__ void prim(const double u[], double& e, double& p, double v[3], double& cs2,
                                          Counts& cnt) const
     {
-        double E = u[0], Mx = u[1], My = u[2], Mz = u[3];
+        const bool small = (u[0] > 0.0) & (u[0] < tiny_value<double>());
+        const double sc = small ? up_scale<double>() : 1.0;
+        double E = u[0] * sc, Mx = u[1] * sc, My = u[2] * sc, Mz = u[3] * sc;
         double M2 = Mx * Mx + My * My + Mz * Mz;
         if (!fixup(E, Mx, My, Mz, M2, cnt)) {
             e = 0.0; p = 0.0; v[0] = 0.0; v[1] = 0.0; v[2] = 0.0; cs2 = 0.0;
@@ -547,6 +631,161 @@ struct EosTable {
         const double iw = Math<double>::rcp(E + p);
         v[0] = Mx * iw; v[1] = My * iw; v[2] = Mz * iw;
         cs2 = dp;
+        if (small) {
+            e = e * down_scale<double>();
+            p = p * down_scale<double>();
+        }
+    }
+};
+
+
+// ---------------------------------------------------------------------------
+// Ideal gas with the conserved charge (Sec. 2.1 closure p = p(e, n)):
+// p = (gamma - 1) max(e - n, 0), n the rest-frame charge density.  FP64, 5
+// components only.
+//
+// con2prim (Sec. 2.6): with e = E - |M|^2 / (E + p) and
+// n = R sqrt(1 - |M|^2 / (E + p)^2) the fixed point for v is the root of
+//   f(p) = (gamma - 1)(e(p) - n(p)) - p,
+// which decreases in p (for gamma <= 2): f' = (gamma - 1) v^2 (1 - R W / (E + p)) - 1.
+// If f(0) <= 0 the gas is cold (p = 0, v = M / E).  Otherwise safeguarded
+// Newton on [0, (gamma - 1) E] from p = f(0): a step leaving the bracket
+// (which shrinks with the sign of f) is replaced by bisection; the solve stops
+// when the correction is below 1e-10 (E + p) and accepts it (quadratic
+// convergence leaves an error far below the rounding of f).
+// ---------------------------------------------------------------------------
+struct EosGamma {
+    static constexpr int kWaves = 3;            // five components: more live state per interface
+    static constexpr bool kLoadLAhead = false;
+    static constexpr int kMaxIter = 60;
+    static constexpr double kTol = 1e-10;
+    double gm1;    // gamma - 1
+    double gam;    // gamma
+
+    static EosGamma make(double gamma)
+    {
+        EosGamma g;
+        g.gam = gamma;
+        g.gm1 = gamma - 1.0;
+        return g;
+    }
+
+    // f(p) and f'(p); iw = 1 / (E + p) out.
+    __device__ __forceinline__ void residual(double E, double M2, double R, double p, double& f, double& fp,
+                                             double& iw) const
+    {
+        iw = Math<double>::rcp(E + p);
+        const double v2 = M2 * iw * iw;
+        const double sq = Math<double>::sqrt(1.0 - v2);   // 1 / W
+        const double e = E - M2 * iw;
+        f = gm1 * (e - R * sq) - p;
+        fp = gm1 * v2 * (1.0 - R * iw * Math<double>::rcp(sq)) - 1.0;
+    }
+
+    // Pressure of a live state (E > 0, |M| < E, R >= 0).
+    __device__ __forceinline__ double pressure(double E, double M2, double R, Counts& cnt) const
+    {
+        if (M2 == 0.0) return gm1 * fmax(E - R, 0.0);
+        double f, fp, iw;
+        residual(E, M2, R, 0.0, f, fp, iw);
+        if (!(f > 0.0)) return 0.0;   // cold gas
+        double lo = 0.0, hi = gm1 * E;
+        double p = fmin(f, hi);
+        for (int it = 1;; it++) {
+            residual(E, M2, R, p, f, fp, iw);
+            const double dp = f * Math<double>::rcp(fp);   // fp < 0
+            double pn = p - dp;
+            cnt.iters += cnt.w;
+            if (fabs(dp) <= kTol * (E + p)) return fmax(pn, 0.0);
+            if (f > 0.0) lo = p;
+            else hi = p;
+            if (!(pn > lo && pn < hi)) pn = 0.5 * (lo + hi);
+            p = pn;
+            if (it >= kMaxIter) return p;
+        }
+    }
+
+    // Guards: E <= 0, a non-finite component or R < 0 -> bad (the zero state:
+    // zero flux); |M| above (1 - 1e-12) E is scaled to that bound.  Returns false
+    // for the zero state.
+    __device__ __forceinline__ bool fixup(double& E, double& Mx, double& My, double& Mz, double& M2, double R,
+                                          Counts& cnt) const
+    {
+        if (!((E > 0.0) & (E <= big_value<double>()) & (M2 <= big_value<double>()) & (R >= 0.0) &
+              (R <= big_value<double>()))) {
+            cnt.bad += cnt.w;
+            return false;
+        }
+        const double Mlim = mmax<double>() * E;
+        if (M2 > Mlim * Mlim) {
+            const double s = Mlim / Math<double>::sqrt_safe(M2);
+            Mx = Mx * s; My = My * s; Mz = Mz * s;
+            M2 = Mx * Mx + My * My + Mz * Mz;
+            cnt.floor_ += cnt.w;
+        }
+        return true;
+    }
+
+    template <int D, int NC = 5>
+    __device__ __forceinline__ void flux(const double u[], double F[], Counts& cnt) const
+    {
+        static_assert(NC == 5, "the ideal gas needs the charge");
+        // near-vacuum states are evaluated scaled up (con2prim of the ideal gas is scale invariant)
+        const bool small = (u[0] > 0.0) & (u[0] < tiny_value<double>());
+        const double sc = small ? up_scale<double>() : 1.0;
+        double E = u[0] * sc, Mx = u[1] * sc, My = u[2] * sc, Mz = u[3] * sc;
+        const double R = u[4] * sc;
+        double M2 = Mx * Mx + My * My + Mz * Mz;
+        if (!fixup(E, Mx, My, Mz, M2, R, cnt)) {
+#pragma unroll
+            for (int c = 0; c < 5; c++) F[c] = 0.0;
+            return;
+        }
+        const double p = pressure(E, M2, R, cnt);
+        const double MD = (D == 0) ? Mx : ((D == 1) ? My : Mz);
+        const double vD = MD * Math<double>::rcp(E + p);
+        F[0] = MD;  // (E + p) v_D
+        F[1] = Mx * vD;
+        F[2] = My * vD;
+        F[3] = Mz * vD;
+        F[1 + D] = F[1 + D] + p;
+        F[4] = R * vD;
+        if (small) {
+#pragma unroll
+            for (int c = 0; c < 5; c++) F[c] = F[c] * down_scale<double>();
+        }
+    }
+
+    template <int D, int NC = 5>
+    __device__ __forceinline__ void flux2(const double uA[], const double uB[], double FA[], double FB[],
+                                          Counts& cnt) const
+    {
+        flux<D, NC>(uA, FA, cnt);
+        flux<D, NC>(uB, FB, cnt);
+    }
+
+    // cs2 = gamma p / (e + p) (0 for cold gas).
+    __device__ __forceinline__ void prim(const double u[], double& e, double& p, double v[3], double& cs2,
+                                         Counts& cnt) const
+    {
+        const bool small = (u[0] > 0.0) & (u[0] < tiny_value<double>());
+        const double sc = small ? up_scale<double>() : 1.0;
+        double E = u[0] * sc, Mx = u[1] * sc, My = u[2] * sc, Mz = u[3] * sc;
+        const double R = u[4] * sc;
+        double M2 = Mx * Mx + My * My + Mz * Mz;
+        if (!fixup(E, Mx, My, Mz, M2, R, cnt)) {
+            e = 0.0; p = 0.0; v[0] = 0.0; v[1] = 0.0; v[2] = 0.0; cs2 = 0.0;
+            return;
+        }
+        p = pressure(E, M2, R, cnt);
+        const double iw = Math<double>::rcp(E + p);
+        v[0] = Mx * iw; v[1] = My * iw; v[2] = Mz * iw;
+        e = E - M2 * iw;
+        cs2 = p > 0.0 ? gam * p * Math<double>::rcp(e + p) : 0.0;
+        if (small) {
+            e = e * down_scale<double>();
+            p = p * down_scale<double>();
+        }
     }
 };
 
@@ -614,31 +853,32 @@ __device__ __forceinline__ T half_slope(T a, T b)
 // ---------------------------------------------------------------------------
 // PAIRED: evaluate the two face fluxes with Eos::flux2 (overlapped table
 // lookups; more registers), else one after the other.
-template <int D, typename T, class Eos, bool PAIRED>
-__device__ __forceinline__ void flux_pair(const Eos& eos, const T uA[4], const T uB[4], T FA[4], T FB[4], Counts& cnt)
+template <int D, typename T, class Eos, bool PAIRED, int NC = 4>
+__device__ __forceinline__ void flux_pair(const Eos& eos, const T uA[], const T uB[], T FA[], T FB[], Counts& cnt)
 {
     if constexpr (PAIRED) {
-        eos.template flux2<D>(uA, uB, FA, FB, cnt);
+        eos.template flux2<D, NC>(uA, uB, FA, FB, cnt);
     } else {
-        eos.template flux<D>(uA, FA, cnt);
-        eos.template flux<D>(uB, FB, cnt);
+        eos.template flux<D, NC>(uA, FA, cnt);
+        eos.template flux<D, NC>(uB, FB, cnt);
     }
 }
 
-template <int D, int LIM, bool PAIRED, typename T, class Eos>
-__device__ __forceinline__ void hancock(const T um[4], const T u0[4], const T up[4], T half_lam,
-                                        T ULt[4], T URt[4], const Eos& eos, Counts& cnt)
+// NC: conserved components (4, or 5 with the charge R).
+template <int D, int LIM, bool PAIRED, int NC = 4, typename T, class Eos>
+__device__ __forceinline__ void hancock(const T um[], const T u0[], const T up[], T half_lam,
+                                        T ULt[], T URt[], const Eos& eos, Counts& cnt)
 {
-    T UL[4], UR[4], FL[4], FR[4];
+    T UL[NC], UR[NC], FL[NC], FR[NC];
 #pragma unroll
-    for (int c = 0; c < 4; c++) {
+    for (int c = 0; c < NC; c++) {
         const T hs = half_slope<LIM>(u0[c] - um[c], up[c] - u0[c]);
         UL[c] = u0[c] - hs;
         UR[c] = u0[c] + hs;
     }
-    flux_pair<D, T, Eos, PAIRED>(eos, UL, UR, FL, FR, cnt);
+    flux_pair<D, T, Eos, PAIRED, NC>(eos, UL, UR, FL, FR, cnt);
 #pragma unroll
-    for (int c = 0; c < 4; c++) {
+    for (int c = 0; c < NC; c++) {
         const T dF = FL[c] - FR[c];   // both faces move by (dt/2dx) dF
         ULt[c] = fma(half_lam, dF, UL[c]);
         URt[c] = fma(half_lam, dF, UR[c]);
@@ -678,22 +918,22 @@ __device__ __forceinline__ void unsplit_faces(const T um[4], const T u0[4], cons
 // (the average's factor 1/2 is exact and is applied with the flux
 // difference, where it folds into the 1/dx factor).
 // ---------------------------------------------------------------------------
-template <int D, bool PAIRED, typename T, class Eos>
-__device__ __forceinline__ void musta(T UL[4], T UR[4], int k, const AxisConst<T>& ac, T G[4],
+template <int D, bool PAIRED, int NC = 4, typename T, class Eos>
+__device__ __forceinline__ void musta(T UL[], T UR[], int k, const AxisConst<T>& ac, T G[],
                                       const Eos& eos, Counts& cnt)
 {
     for (int l = 1;; l++) {
-        T FL[4], FR[4], Us[4], Flw[4];
-        flux_pair<D, T, Eos, PAIRED>(eos, UL, UR, FL, FR, cnt);
+        T FL[NC], FR[NC], Us[NC], Flw[NC];
+        flux_pair<D, T, Eos, PAIRED, NC>(eos, UL, UR, FL, FR, cnt);
 #pragma unroll
-        for (int c = 0; c < 4; c++) Us[c] = T(0.5) * (UL[c] + UR[c]) - ac.half_alam * (FR[c] - FL[c]);
-        eos.template flux<D>(Us, Flw, cnt);
+        for (int c = 0; c < NC; c++) Us[c] = T(0.5) * (UL[c] + UR[c]) - ac.half_alam * (FR[c] - FL[c]);
+        eos.template flux<D, NC>(Us, Flw, cnt);
 #pragma unroll
-        for (int c = 0; c < 4; c++)
+        for (int c = 0; c < NC; c++)
             G[c] = fma(T(0.5), FL[c] + FR[c], fma(-ac.inv_2alam, UR[c] - UL[c], Flw[c]));
         if (l >= k) break;
 #pragma unroll
-        for (int c = 0; c < 4; c++) {
+        for (int c = 0; c < NC; c++) {
             UL[c] = UL[c] - ac.lam * fma(T(0.5), G[c], -FL[c]);   // F - F_L
             UR[c] = UR[c] - ac.lam * fma(T(-0.5), G[c], FR[c]);   // F_R - F
         }

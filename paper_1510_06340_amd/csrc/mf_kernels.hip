@@ -26,7 +26,7 @@
 namespace mf {
 
 template <typename T>
-__device__ __forceinline__ void load4(const T* const u[4], int64_t i, T w[4])
+__device__ __forceinline__ void load4(const T* const u[], int64_t i, T w[4])
 {
     w[0] = u[0][i]; w[1] = u[1][i]; w[2] = u[2][i]; w[3] = u[3][i];
 }
@@ -35,6 +35,21 @@ template <typename T>
 __device__ __forceinline__ void copy4(const T a[4], T b[4])
 {
     b[0] = a[0]; b[1] = a[1]; b[2] = a[2]; b[3] = a[3];
+}
+
+// NC conserved components (4, or 5 with the charge R) of cell i.
+template <int NC, typename T>
+__device__ __forceinline__ void loadn(const T* const u[], int64_t i, T w[])
+{
+#pragma unroll
+    for (int c = 0; c < NC; c++) w[c] = u[c][i];
+}
+
+template <int NC, typename T>
+__device__ __forceinline__ void copyn(const T a[], T b[])
+{
+#pragma unroll
+    for (int c = 0; c < NC; c++) b[c] = a[c];
 }
 
 __device__ __forceinline__ void add_counts(Counts& a, const Counts& b)
@@ -95,45 +110,45 @@ constexpr int sweep_mode()
 // add the source, apply the Runge-Kutta combine and track the max speed.
 // uin = U[cell] of the stage input, Lp = L so far, ub = RK base state,
 // SE = energy source of the cell (jet only; jet_source below).
-template <typename T, bool JET, int MODE, class Eos>
-__device__ __forceinline__ void emit_cell(const SweepArgs<T>& a, const Eos& eos, int64_t ij, const T uin[4],
-                                          const T Ld[4], const T Lp[4], const T ub[4], T SE, T& smax)
+template <typename T, bool JET, int MODE, int NC = 4, class Eos>
+__device__ __forceinline__ void emit_cell(const SweepArgs<T>& a, const Eos& eos, int64_t ij, const T uin[],
+                                          const T Ld[], const T Lp[], const T ub[], T SE, T& smax)
 {
     if constexpr (MODE == SW_WRITE) {
 #pragma unroll
-        for (int c = 0; c < 4; c++) a.L[c][ij] = Ld[c];
+        for (int c = 0; c < NC; c++) a.L[c][ij] = Ld[c];
         return;
     }
     if constexpr (MODE == SW_ACCUM) {
 #pragma unroll
-        for (int c = 0; c < 4; c++) a.L[c][ij] = Lp[c] + Ld[c];
+        for (int c = 0; c < NC; c++) a.L[c][ij] = Lp[c] + Ld[c];
         return;
     }
-    T Lt[4];
+    T Lt[NC];
 #pragma unroll
-    for (int c = 0; c < 4; c++) Lt[c] = Lp[c] + Ld[c];
+    for (int c = 0; c < NC; c++) Lt[c] = Lp[c] + Ld[c];
     if constexpr (JET) {
         Lt[0] = Lt[0] + SE;
         Lt[1] = Lt[1] + T(a.jet_v) * SE;
     }
-    T o[4];
+    T o[NC];
     const T dt = a.dt;
     if (a.kind == RK_FIRST) {
 #pragma unroll
-        for (int c = 0; c < 4; c++) o[c] = uin[c] + dt * Lt[c];
+        for (int c = 0; c < NC; c++) o[c] = uin[c] + dt * Lt[c];
     } else if (a.kind == RK2_LAST) {
 #pragma unroll
-        for (int c = 0; c < 4; c++) o[c] = T(0.5) * ((ub[c] + uin[c]) + dt * Lt[c]);
+        for (int c = 0; c < NC; c++) o[c] = T(0.5) * ((ub[c] + uin[c]) + dt * Lt[c]);
     } else if (a.kind == RK3_MID) {
 #pragma unroll
-        for (int c = 0; c < 4; c++) o[c] = (T(0.75) * ub[c] + T(0.25) * uin[c]) + T(0.25) * (dt * Lt[c]);
+        for (int c = 0; c < NC; c++) o[c] = (T(0.75) * ub[c] + T(0.25) * uin[c]) + T(0.25) * (dt * Lt[c]);
     } else {
         const T third = T(1.0 / 3.0), two3 = T(2.0 / 3.0);
 #pragma unroll
-        for (int c = 0; c < 4; c++) o[c] = (third * ub[c] + two3 * uin[c]) + two3 * (dt * Lt[c]);
+        for (int c = 0; c < NC; c++) o[c] = (third * ub[c] + two3 * uin[c]) + two3 * (dt * Lt[c]);
     }
 #pragma unroll
-    for (int c = 0; c < 4; c++) a.out[c][ij] = o[c];
+    for (int c = 0; c < NC; c++) a.out[c][ij] = o[c];
     if (a.want_smax) {
         T e, p, v[3], cs2;
         Counts cs;
@@ -177,7 +192,8 @@ __device__ __forceinline__ float shift_up1(float v, float carry)
 // One thread's segment [s0, s0 + seg) of grid line 'line' along axis D.
 // UNSPLIT (the MF_FLAG_UNSPLIT_HANCOCK ablation): the faces take the cell's
 // three-axis correction from a.dl instead of this axis' Hancock term.
-template <typename T, int D, int LIM, class Eos, bool JET, bool UNSPLIT = false>
+// NC: conserved components (4, or 5 with the charge R).
+template <typename T, int D, int LIM, class Eos, bool JET, bool UNSPLIT = false, int NC = 4>
 __device__ __forceinline__ void sweep_line(const SweepArgs<T>& a, const Eos& eos, int64_t line, int s0,
                                            Counts& cnt, T& smax)
 {
@@ -205,19 +221,20 @@ __device__ __forceinline__ void sweep_line(const SweepArgs<T>& a, const Eos& eos
         jet_dxy2 = x * x + y * y;
     }
 
-    T w0[4], w1[4], w2[4], wn[4];
-    T ULt[4], URt[4], URp[4], Fp[4], Fn[4];
-    load4(a.u, cell(s0 - 2), w1);
-    load4(a.u, cell(s0 - 1), w2);
-    load4(a.u, cell(s0), wn);
+    static_assert(NC == 4 || !UNSPLIT, "the unsplit ablation carries four components");
+    T w0[NC], w1[NC], w2[NC], wn[NC];
+    T ULt[NC], URt[NC], URp[NC], Fp[NC], Fn[NC];
+    loadn<NC>(a.u, cell(s0 - 2), w1);
+    loadn<NC>(a.u, cell(s0 - 1), w2);
+    loadn<NC>(a.u, cell(s0), wn);
     for (int j = s0 - 2; j < s1; j++) {
-        copy4(w1, w0);
-        copy4(w2, w1);
-        copy4(wn, w2);
+        copyn<NC>(w1, w0);
+        copyn<NC>(w2, w1);
+        copyn<NC>(wn, w2);
         // cell j+3 is loaded one step ahead (its latency hides behind this
         // step); march_ahead keeps the last iteration's load, whose value is
         // never used, inside the line
-        load4(a.u, cell(march_ahead(j, N)), wn);
+        loadn<NC>(a.u, cell(march_ahead(j, N)), wn);
         const int64_t ij = base + (int64_t)j * sd;
         const bool body = j >= s0;
         constexpr int MODE = sweep_mode<D>();
@@ -225,9 +242,11 @@ __device__ __forceinline__ void sweep_line(const SweepArgs<T>& a, const Eos& eos
         // cell's work, whose latency it hides behind (the z sweep has no
         // registers to spare)
         constexpr bool early_L = MODE == SW_ACCUM && Eos::kLoadLAhead;
-        T Lp[4] = {T(0), T(0), T(0), T(0)};
+        T Lp[NC];
+#pragma unroll
+        for (int c = 0; c < NC; c++) Lp[c] = T(0);
         if constexpr (early_L) {
-            if (body) load4((const T* const*)a.L, ij, Lp);
+            if (body) loadn<NC>((const T* const*)a.L, ij, Lp);
         }
         // the jet source of cell j, evaluated here where few values are live
         T SE = T(0);
@@ -249,32 +268,32 @@ __device__ __forceinline__ void sweep_line(const SweepArgs<T>& a, const Eos& eos
             load_dl(a.dl + ebase + (int64_t)(j + 2) * a.estride_d, a.dl_n, d);
             unsplit_faces<LIM>(w0, w1, w2, d, ULt, URt);
         } else {
-            hancock<D, LIM, true>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, cnt);
+            hancock<D, LIM, true, NC>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, cnt);
         }
         if (j == s0 - 2) {
-            copy4(URt, URp);
+            copyn<NC>(URt, URp);
             continue;
         }
         // interface j + 1/2; counted once over all segments (interfaces -1/2..N-1/2)
         cnt.w = (body || s0 == 0) ? 1u : 0u;
-        musta<D, true>(URp, ULt, a.k, a.ac, Fn, eos, cnt);
-        copy4(URt, URp);
+        musta<D, true, NC>(URp, ULt, a.k, a.ac, Fn, eos, cnt);
+        copyn<NC>(URt, URp);
         if (!body) {
-#pragma unroll
-            for (int c = 0; c < 4; c++) Fp[c] = Fn[c];
+            copyn<NC>(Fn, Fp);
             continue;
         }
 
-        T Ld[4], ub[4] = {T(0), T(0), T(0), T(0)};
-        if constexpr (MODE != SW_WRITE && !early_L) load4((const T* const*)a.L, ij, Lp);
+        T Ld[NC], ub[NC];
+#pragma unroll
+        for (int c = 0; c < NC; c++) ub[c] = T(0);
+        if constexpr (MODE != SW_WRITE && !early_L) loadn<NC>((const T* const*)a.L, ij, Lp);
         if constexpr (MODE == SW_FINAL) {
-            if (a.kind != RK_FIRST) load4(a.u0, ij, ub);
+            if (a.kind != RK_FIRST) loadn<NC>(a.u0, ij, ub);
         }
 #pragma unroll
-        for (int c = 0; c < 4; c++) Ld[c] = -(Fn[c] - Fp[c]) * a.ac.inv_2dx;   // Fn, Fp: G = 2 F
-        emit_cell<T, JET, MODE>(a, eos, ij, w0, Ld, Lp, ub, SE, smax);
-#pragma unroll
-        for (int c = 0; c < 4; c++) Fp[c] = Fn[c];
+        for (int c = 0; c < NC; c++) Ld[c] = -(Fn[c] - Fp[c]) * a.ac.inv_2dx;   // Fn, Fp: G = 2 F
+        emit_cell<T, JET, MODE, NC>(a, eos, ij, w0, Ld, Lp, ub, SE, smax);
+        copyn<NC>(Fn, Fp);
     }
 }
 
@@ -286,13 +305,13 @@ constexpr int sweep_waves()
     return JET && Eos::kWaves > 3 ? 3 : Eos::kWaves;
 }
 
-template <typename T, int D, int LIM, class Eos, bool JET, bool UNSPLIT = false>
+template <typename T, int D, int LIM, class Eos, bool JET, bool UNSPLIT = false, int NC = 4>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_waves<Eos, JET>()))) void k_sweep(SweepArgs<T> a, Eos eos)
 {
     const int64_t line = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     Counts cnt;
     T smax = T(0);
-    sweep_line<T, D, LIM, Eos, JET, UNSPLIT>(a, eos, line, (int)blockIdx.y * a.seg, cnt, smax);
+    sweep_line<T, D, LIM, Eos, JET, UNSPLIT, NC>(a, eos, line, (int)blockIdx.y * a.seg, cnt, smax);
     flush_stats(a.stats, cnt, smax, sweep_mode<D>() == SW_FINAL && a.want_smax);
 }
 
@@ -312,10 +331,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_waves
 constexpr bool kPairX = false;
 
 // Wavefront 'wave' of the x sweep: items [wave * 64 * seg, ...) of the row stream.
-// carry: this wavefront's 8 LDS slots, through which lane 63 hands its right
+// carry: this wavefront's 2 NC LDS slots, through which lane 63 hands its right
 // face state and flux to lane 0 of the next chunk (LDS traffic instead of
 // lane reads into scalar registers and moves back).
-template <typename T, int LIM, class Eos, bool UNSPLIT = false>
+template <typename T, int LIM, class Eos, bool UNSPLIT = false, int NC = 4>
 __device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& eos, int64_t wave, int lane,
                                              T* carry, Counts& cnt, T& smax)
 {
@@ -336,7 +355,7 @@ __device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& e
         }
         if (lane == 63) {
 #pragma unroll
-            for (int c = 0; c < 8; c++) carry[c] = T(0);
+            for (int c = 0; c < 2 * NC; c++) carry[c] = T(0);
         }
         __builtin_amdgcn_wave_barrier();
         for (int64_t c0 = s - 2; c0 < e; c0 += 64) {
@@ -344,21 +363,22 @@ __device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& e
             const bool valid = (it >= 0) & (it < e);
             const int64_t base = (valid ? row : 0) * (int64_t)N;
             const int xc = valid ? x : 0;
-            T w0[4], w1[4], w2[4];
+            static_assert(NC == 4 || !UNSPLIT, "the unsplit ablation carries four components");
+            T w0[NC], w1[NC], w2[NC];
             // chunks away from row edges (most of them) need no ghost mapping:
             // the neighbours are the adjacent elements
             const uint64_t edge = lanes_where(!valid) | lanes_where(xc < 1) | lanes_where(xc > N - 2);
             if (edge == 0) {
                 const int64_t ic = base + xc;
-                load4(a.u, ic - 1, w0);
-                load4(a.u, ic, w1);
-                load4(a.u, ic + 1, w2);
+                loadn<NC>(a.u, ic - 1, w0);
+                loadn<NC>(a.u, ic, w1);
+                loadn<NC>(a.u, ic + 1, w2);
             } else {
-                load4(a.u, base + ghost(xc - 1, N, a.periodic), w0);
-                load4(a.u, base + ghost(xc, N, a.periodic), w1);
-                load4(a.u, base + ghost(xc + 1, N, a.periodic), w2);
+                loadn<NC>(a.u, base + ghost(xc - 1, N, a.periodic), w0);
+                loadn<NC>(a.u, base + ghost(xc, N, a.periodic), w1);
+                loadn<NC>(a.u, base + ghost(xc + 1, N, a.periodic), w2);
             }
-            T ULt[4], URt[4];
+            T ULt[NC], URt[NC];
             cnt.w = (valid & (it >= s)) ? 1u : 0u;
             if constexpr (UNSPLIT) {
                 // the lane's cell xc in [-1, N] of row (y, z) = (r % ny, r / ny), r in [0, ny nz)
@@ -369,32 +389,38 @@ __device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& e
                 load_dl(a.dl + e, a.dl_n, d);
                 unsplit_faces<LIM>(w0, w1, w2, d, ULt, URt);
             } else {
-                hancock<0, LIM, kPairX>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, cnt);
+                hancock<0, LIM, kPairX, NC>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, cnt);
             }
-            T URl[4];
+            T URl[NC];
 #pragma unroll
-            for (int c = 0; c < 4; c++) URl[c] = shift_up1(URt[c], carry[c]);
-            T F[4] = {T(0), T(0), T(0), T(0)};
+            for (int c = 0; c < NC; c++) URl[c] = shift_up1(URt[c], carry[c]);
+            T F[NC];
+#pragma unroll
+            for (int c = 0; c < NC; c++) F[c] = T(0);
             if (valid & (x >= 0) & (it >= s - 1)) {   // interface x - 1/2
                 cnt.w = (it >= s) ? 1u : 0u;
-                musta<0, kPairX>(URl, ULt, a.k, a.ac, F, eos, cnt);
+                musta<0, kPairX, NC>(URl, ULt, a.k, a.ac, F, eos, cnt);
             }
-            T Fl[4];
+            T Fl[NC];
 #pragma unroll
-            for (int c = 0; c < 4; c++) Fl[c] = shift_up1(F[c], carry[4 + c]);
+            for (int c = 0; c < NC; c++) Fl[c] = shift_up1(F[c], carry[NC + c]);
             if (valid & (x >= 1) & (it >= s)) {   // cell x - 1
                 const int64_t ij = base + (x - 1);
-                T Ld[4], Lp[4] = {T(0), T(0), T(0), T(0)}, ub[4] = {T(0), T(0), T(0), T(0)};
+                T Ld[NC], Lp[NC], ub[NC];
 #pragma unroll
-                for (int c = 0; c < 4; c++) Ld[c] = -(F[c] - Fl[c]) * a.ac.inv_2dx;   // F, Fl: G = 2 F
-                emit_cell<T, false, SW_WRITE>(a, eos, ij, w0, Ld, Lp, ub, T(0), smax);
+                for (int c = 0; c < NC; c++) {
+                    Ld[c] = -(F[c] - Fl[c]) * a.ac.inv_2dx;   // F, Fl: G = 2 F
+                    Lp[c] = T(0);
+                    ub[c] = T(0);
+                }
+                emit_cell<T, false, SW_WRITE, NC>(a, eos, ij, w0, Ld, Lp, ub, T(0), smax);
             }
             __builtin_amdgcn_wave_barrier();   // every lane has read the carry
             if (lane == 63) {
 #pragma unroll
-                for (int c = 0; c < 4; c++) {
+                for (int c = 0; c < NC; c++) {
                     carry[c] = URt[c];
-                    carry[4 + c] = F[c];
+                    carry[NC + c] = F[c];
                 }
             }
             __builtin_amdgcn_wave_barrier();
@@ -407,14 +433,14 @@ __device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& e
     }
 }
 
-template <typename T, int LIM, class Eos, bool UNSPLIT = false>
+template <typename T, int LIM, class Eos, bool UNSPLIT = false, int NC = 4>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Eos::kWaves))) void k_sweep_x(SweepArgs<T> a, Eos eos)
 {
-    __shared__ T carry[256 / 64][8];
+    __shared__ T carry[256 / 64][2 * NC];
     Counts cnt;
     T smax = T(0);
-    sweep_x_wave<T, LIM, Eos, UNSPLIT>(a, eos, ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6, threadIdx.x & 63,
-                              carry[threadIdx.x >> 6], cnt, smax);
+    sweep_x_wave<T, LIM, Eos, UNSPLIT, NC>(a, eos, ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6,
+                                           threadIdx.x & 63, carry[threadIdx.x >> 6], cnt, smax);
     flush_stats(a.stats, cnt, smax, false);   // the x sweep writes L only
 }
 
@@ -560,18 +586,31 @@ __global__ void k_fill_u32(unsigned int* p, int n, unsigned int v)
 // ---------------------------------------------------------------------------
 // Standalone con2prim (Sec. 2.6) over n states.
 // ---------------------------------------------------------------------------
-template <typename T, class Eos>
+// With the charge (NC = 5) the rest-frame density n = R sqrt(1 - v^2) goes to prim[5].
+template <typename T, class Eos, int NC = 4>
 __global__ __launch_bounds__(256) void k_con2prim(C2PArgs<T> a, Eos eos)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     Counts cnt;
     if (i < a.n) {
-        T u[4] = {a.U[0][i], a.U[1][i], a.U[2][i], a.U[3][i]};
+        T u[NC];
+        loadn<NC>(a.U, i, u);
         T e, p, v[3], cs2;
         Counts c1;
         eos.prim(u, e, p, v, cs2, c1);
         a.prim[0][i] = e; a.prim[1][i] = p;
         a.prim[2][i] = v[0]; a.prim[3][i] = v[1]; a.prim[4][i] = v[2];
+        if constexpr (NC == 5) {
+            // a non-finite charge makes the state bad; a zero state has n = 0 like its other primitives
+            bool live = c1.bad == 0;
+            if (live && !(fabs(u[4]) <= big_value<T>())) {
+                c1.bad += 1;
+                live = false;
+                a.prim[0][i] = T(0); a.prim[1][i] = T(0);
+                a.prim[2][i] = T(0); a.prim[3][i] = T(0); a.prim[4][i] = T(0);
+            }
+            a.prim[5][i] = live ? u[4] * Math<T>::sqrt(T(1) - (v[0] * v[0] + v[1] * v[1] + v[2] * v[2])) : T(0);
+        }
         if (a.iters) a.iters[i] = (int32_t)c1.iters;
         add_counts(cnt, c1);
     }
@@ -582,53 +621,58 @@ __global__ __launch_bounds__(256) void k_con2prim(C2PArgs<T> a, Eos eos)
 // Conservation sums: fixed assignment of cells to threads, fixed-order tree
 // in LDS, one partial per block; the final kernel sums the partials in order.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int NC>
 __global__ __launch_bounds__(256) void k_totals_partial(TotalsArgs<T> a)
 {
-    __shared__ double sh[4][256];
+    __shared__ double sh[NC][256];
     const int t = threadIdx.x;
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    double s[NC];
+#pragma unroll
+    for (int c = 0; c < NC; c++) s[c] = 0.0;
     const int64_t chunk = (a.n + gridDim.x - 1) / gridDim.x;
     const int64_t lo = (int64_t)blockIdx.x * chunk;
     const int64_t hi = min(lo + chunk, a.n);
     for (int64_t i = lo + t; i < hi; i += 256) {
 #pragma unroll
-        for (int c = 0; c < 4; c++) s[c] += (double)a.U[c][i];
+        for (int c = 0; c < NC; c++) s[c] += (double)a.U[c][i];
     }
 #pragma unroll
-    for (int c = 0; c < 4; c++) sh[c][t] = s[c];
+    for (int c = 0; c < NC; c++) sh[c][t] = s[c];
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (t < w) {
 #pragma unroll
-            for (int c = 0; c < 4; c++) sh[c][t] += sh[c][t + w];
+            for (int c = 0; c < NC; c++) sh[c][t] += sh[c][t + w];
         }
         __syncthreads();
     }
-    if (t < 4) a.partial[(int64_t)blockIdx.x * 4 + t] = sh[t][0];
+    if (t < NC) a.partial[(int64_t)blockIdx.x * NC + t] = sh[t][0];
 }
 
+template <int NC>
 __global__ __launch_bounds__(256) void k_totals_final(const double* partial, int nblocks, double dV,
                                                        double* out)
 {
-    __shared__ double sh[4][256];
+    __shared__ double sh[NC][256];
     const int t = threadIdx.x;
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    double s[NC];
+#pragma unroll
+    for (int c = 0; c < NC; c++) s[c] = 0.0;
     for (int b = t; b < nblocks; b += 256) {
 #pragma unroll
-        for (int c = 0; c < 4; c++) s[c] += partial[(int64_t)b * 4 + c];
+        for (int c = 0; c < NC; c++) s[c] += partial[(int64_t)b * NC + c];
     }
 #pragma unroll
-    for (int c = 0; c < 4; c++) sh[c][t] = s[c];
+    for (int c = 0; c < NC; c++) sh[c][t] = s[c];
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (t < w) {
 #pragma unroll
-            for (int c = 0; c < 4; c++) sh[c][t] += sh[c][t + w];
+            for (int c = 0; c < NC; c++) sh[c][t] += sh[c][t + w];
         }
         __syncthreads();
     }
-    if (t < 4) out[t] = sh[t][0] * dV;
+    if (t < NC) out[t] = sh[t][0] * dV;
 }
 
 __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v)
@@ -806,12 +850,14 @@ hipError_t launch_con2prim(int64_t n, hipStream_t s, const C2PArgs<T>& a, const 
 }
 
 template <typename T>
-hipError_t launch_totals(hipStream_t s, const TotalsArgs<T>& a, int nblocks, double dV, double* out)
+hipError_t launch_totals(hipStream_t s, const TotalsArgs<T>& a, int nc, int nblocks, double dV, double* out)
 {
-    hipLaunchKernelGGL((k_totals_partial<T>), dim3(nblocks), dim3(256), 0, s, a);
+    if (nc == 5) hipLaunchKernelGGL((k_totals_partial<T, 5>), dim3(nblocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_totals_partial<T, 4>), dim3(nblocks), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(256), 0, s, a.partial, nblocks, dV, out);
+    if (nc == 5) hipLaunchKernelGGL(k_totals_final<5>, dim3(1), dim3(256), 0, s, a.partial, nblocks, dV, out);
+    else hipLaunchKernelGGL(k_totals_final<4>, dim3(1), dim3(256), 0, s, a.partial, nblocks, dV, out);
     return hipGetLastError();
 }
 
@@ -899,6 +945,101 @@ hipError_t launch_fill_u32(hipStream_t s, unsigned int* p, int n, unsigned int v
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Sweeps with the conserved charge (5 components; FP64, per event, no jet):
+// p = e/3 with a passive charge (EosIdeal<double>) or the ideal gas (EosGamma).
+// ---------------------------------------------------------------------------
+template <int D, int LIM, class Eos>
+static hipError_t launch_charge_lim(dim3 grid, dim3 block, hipStream_t s, const SweepArgs<double>& a, const Eos& eos)
+{
+    if constexpr (D == 0) hipLaunchKernelGGL((k_sweep_x<double, LIM, Eos, false, 5>), grid, block, 0, s, a, eos);
+    else hipLaunchKernelGGL((k_sweep<double, D, LIM, Eos, false, false, 5>), grid, block, 0, s, a, eos);
+    return hipGetLastError();
+}
+
+template <int D, int LIM, class Eos>
+static int charge_waves_lim(int block)
+{
+    static int w[3] = {0, 0, 0};  // by block size 64 / 128 / 256
+    const int bi = block == 64 ? 0 : (block == 128 ? 1 : 2);
+    if (w[bi] == 0) {
+        int nb = 0;
+        const void* k = D == 0 ? reinterpret_cast<const void*>(&k_sweep_x<double, LIM, Eos, false, 5>)
+                               : reinterpret_cast<const void*>(&k_sweep<double, D, LIM, Eos, false, false, 5>);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, block, 0) != hipSuccess || nb < 1) nb = 1;
+        w[bi] = std::max(1, nb * (block / 64) / 4);
+    }
+    return w[bi];
+}
+
+template <int LIM, class Eos>
+static hipError_t launch_charge_axis(int axis, dim3 grid, dim3 block, hipStream_t s, const SweepArgs<double>& a,
+                                     const Eos& eos)
+{
+    switch (axis) {
+    case 0: return launch_charge_lim<0, LIM>(grid, block, s, a, eos);
+    case 1: return launch_charge_lim<1, LIM>(grid, block, s, a, eos);
+    case 2: return launch_charge_lim<2, LIM>(grid, block, s, a, eos);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int LIM, class Eos>
+static int charge_waves_axis(int axis, int block)
+{
+    switch (axis) {
+    case 0: return charge_waves_lim<0, LIM, Eos>(block);
+    case 1: return charge_waves_lim<1, LIM, Eos>(block);
+    default: return charge_waves_lim<2, LIM, Eos>(block);
+    }
+}
+
+template <class Eos>
+hipError_t launch_sweep_charge(int axis, int lim, dim3 grid, dim3 block, hipStream_t s, const SweepArgs<double>& a,
+                               const Eos& eos)
+{
+    switch (lim) {
+    case LIM_NONE: return launch_charge_axis<LIM_NONE>(axis, grid, block, s, a, eos);
+    case LIM_MINMOD: return launch_charge_axis<LIM_MINMOD>(axis, grid, block, s, a, eos);
+    case LIM_SUPERBEE: return launch_charge_axis<LIM_SUPERBEE>(axis, grid, block, s, a, eos);
+    case LIM_MC: return launch_charge_axis<LIM_MC>(axis, grid, block, s, a, eos);
+    case LIM_VANLEER: return launch_charge_axis<LIM_VANLEER>(axis, grid, block, s, a, eos);
+    case LIM_VANALBADA: return launch_charge_axis<LIM_VANALBADA>(axis, grid, block, s, a, eos);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <class Eos>
+int sweep_waves_per_simd_charge(int axis, int lim, int block)
+{
+    switch (lim) {
+    case LIM_NONE: return charge_waves_axis<LIM_NONE, Eos>(axis, block);
+    case LIM_MINMOD: return charge_waves_axis<LIM_MINMOD, Eos>(axis, block);
+    case LIM_SUPERBEE: return charge_waves_axis<LIM_SUPERBEE, Eos>(axis, block);
+    case LIM_MC: return charge_waves_axis<LIM_MC, Eos>(axis, block);
+    case LIM_VANLEER: return charge_waves_axis<LIM_VANLEER, Eos>(axis, block);
+    default: return charge_waves_axis<LIM_VANALBADA, Eos>(axis, block);
+    }
+}
+
+template <class Eos>
+hipError_t launch_con2prim_charge(int64_t n, hipStream_t s, const C2PArgs<double>& a, const Eos& eos)
+{
+    const int64_t nb = (n + 255) / 256;
+    hipLaunchKernelGGL((k_con2prim<double, Eos, 5>), dim3((unsigned)nb), dim3(256), 0, s, a, eos);
+    return hipGetLastError();
+}
+
+template hipError_t launch_sweep_charge<EosIdeal<double>>(int, int, dim3, dim3, hipStream_t, const SweepArgs<double>&,
+                                                          const EosIdeal<double>&);
+template hipError_t launch_sweep_charge<EosGamma>(int, int, dim3, dim3, hipStream_t, const SweepArgs<double>&,
+                                                  const EosGamma&);
+template int sweep_waves_per_simd_charge<EosIdeal<double>>(int, int, int);
+template int sweep_waves_per_simd_charge<EosGamma>(int, int, int);
+template hipError_t launch_con2prim_charge<EosIdeal<double>>(int64_t, hipStream_t, const C2PArgs<double>&,
+                                                             const EosIdeal<double>&);
+template hipError_t launch_con2prim_charge<EosGamma>(int64_t, hipStream_t, const C2PArgs<double>&, const EosGamma&);
+
 template hipError_t launch_batch_sweep<double, EosIdeal<double>>(int, int, bool, const SweepArgs<double>*,
                                                                  const int64_t*, int, unsigned int*, int64_t, int,
                                                                  hipStream_t, const EosIdeal<double>&);
@@ -936,7 +1077,7 @@ template hipError_t launch_con2prim<float, EosIdeal<float>>(int64_t, hipStream_t
                                                             const EosIdeal<float>&);
 template hipError_t launch_con2prim<double, EosTable>(int64_t, hipStream_t, const C2PArgs<double>&,
                                                       const EosTable&);
-template hipError_t launch_totals<double>(hipStream_t, const TotalsArgs<double>&, int, double, double*);
-template hipError_t launch_totals<float>(hipStream_t, const TotalsArgs<float>&, int, double, double*);
+template hipError_t launch_totals<double>(hipStream_t, const TotalsArgs<double>&, int, int, double, double*);
+template hipError_t launch_totals<float>(hipStream_t, const TotalsArgs<float>&, int, int, double, double*);
 
 }  // namespace mf

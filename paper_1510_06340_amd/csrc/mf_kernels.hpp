@@ -32,9 +32,21 @@ hipError_t launch_sweep_unsplit(int axis, int lim, bool jet, dim3 grid, dim3 blo
 template <typename T, class Eos>
 int sweep_waves_per_simd(int axis, int lim, bool jet, int block);
 
-// Deterministic sums of the four components over a.n cells, times dV, into out[4] (device).
+// Deterministic sums of the nc (4 or 5) components over a.n cells, times dV, into out[nc] (device);
+// a.partial holds kMaxComp doubles per block.
 template <typename T>
-hipError_t launch_totals(hipStream_t s, const TotalsArgs<T>& a, int nblocks, double dV, double* out);
+hipError_t launch_totals(hipStream_t s, const TotalsArgs<T>& a, int nc, int nblocks, double dV, double* out);
+
+// With the conserved charge R (five components; FP64, per event, no jet and
+// no unsplit ablation): Eos = EosIdeal<double> (a passive charge) or EosGamma.
+template <class Eos>
+hipError_t launch_sweep_charge(int axis, int lim, dim3 grid, dim3 block, hipStream_t s, const SweepArgs<double>& a,
+                               const Eos& eos);
+template <class Eos>
+int sweep_waves_per_simd_charge(int axis, int lim, int block);
+// con2prim of n states with the charge: a.U has 5 arrays, a.prim 6 (n = R sqrt(1 - v^2) last).
+template <class Eos>
+hipError_t launch_con2prim_charge(int64_t n, hipStream_t s, const C2PArgs<double>& a, const Eos& eos);
 
 hipError_t launch_fill_u64(hipStream_t s, unsigned long long* p, int64_t n, unsigned long long v);
 hipError_t launch_fill_u32(hipStream_t s, unsigned int* p, int n, unsigned int v);

@@ -6,6 +6,9 @@
 
 namespace mf {
 
+// Conserved components per cell: E, Mx, My, Mz, and with the charge R (Sec. 2.1).
+constexpr int kMaxComp = 5;
+
 // Scheme constants of one sweep axis d (lambda = dt / dx_d).
 template <typename T> struct AxisConst {
     T lam;        // dt / dx_d            (MUSTA predictor; alpha dt / dx_d as an ablation)
@@ -35,10 +38,11 @@ enum { RK_FIRST = 0, RK2_LAST = 1, RK3_MID = 2, RK3_LAST = 3 };
 enum { SW_WRITE = 0, SW_ACCUM = 1, SW_FINAL = 2 };
 
 template <typename T> struct SweepArgs {
-    const T* u[4];      // stage input state (read with the stencil)
-    T* L[4];            // flux-divergence accumulator
-    const T* u0[4];     // Runge-Kutta base state U^n (SW_FINAL, kinds > RK_FIRST)
-    T* out[4];          // stage output (SW_FINAL)
+    // per component (4, or 5 with the charge R)
+    const T* u[kMaxComp];    // stage input state (read with the stencil)
+    T* L[kMaxComp];          // flux-divergence accumulator
+    const T* u0[kMaxComp];   // Runge-Kutta base state U^n (SW_FINAL, kinds > RK_FIRST)
+    T* out[kMaxComp];        // stage output (SW_FINAL)
     int64_t nlines;     // lines along the sweep axis
     int64_t stride_d;   // element stride along the sweep axis
     int64_t stride_f;   // stride of the fast line axis
@@ -86,17 +90,17 @@ template <typename T> struct UnsplitArgs {
 };
 
 template <typename T> struct C2PArgs {
-    const T* U[4];      // E, Mx, My, Mz
-    T* prim[5];         // e, p, vx, vy, vz
+    const T* U[kMaxComp];      // E, Mx, My, Mz (and R with the charge)
+    T* prim[kMaxComp + 1];     // e, p, vx, vy, vz (and n with the charge)
     int32_t* iters;     // nullable
     int64_t n;
     unsigned long long* stats;
 };
 
 template <typename T> struct TotalsArgs {
-    const T* U[4];
+    const T* U[kMaxComp];
     int64_t n;
-    double* partial;    // 4 per block
+    double* partial;    // kMaxComp per block
 };
 
 

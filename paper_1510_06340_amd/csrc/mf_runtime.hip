@@ -9,6 +9,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/mf.h"
@@ -38,10 +39,11 @@ constexpr int kTotalsBlocks = 512;
 struct Event {
     mf_grid_desc d;
     int64_t ncell = 0;
-    void* U[4] = {nullptr, nullptr, nullptr, nullptr};   // caller-owned
-    void* U1[4] = {nullptr, nullptr, nullptr, nullptr};  // RK stage 1 output
-    void* U2[4] = {nullptr, nullptr, nullptr, nullptr};  // RK3 stage 2 output
-    void* L[4] = {nullptr, nullptr, nullptr, nullptr};   // flux-divergence accumulator
+    int nc = 4;                        // conserved components: 4, or 5 with the charge R
+    void* U[kMaxComp] = {};            // caller-owned
+    void* U1[kMaxComp] = {};           // RK stage 1 output
+    void* U2[kMaxComp] = {};           // RK3 stage 2 output
+    void* L[kMaxComp] = {};            // flux-divergence accumulator
     void* DL = nullptr;  // MF_FLAG_UNSPLIT_HANCOCK: 4 (n0+2)(n1+2)(n2+2) corrections
     int64_t dl_n = 0;    // (n0+2)(n1+2)(n2+2)
     double t = 0.0;
@@ -61,6 +63,7 @@ struct mf_grid_s {
     int eos_kind = -1;
     double cs2 = 1.0 / 3.0;
     EosTable table{};               // device view of the tabulated EoS
+    double gamma = 5.0 / 3.0;       // MF_EOS_GAMMA: adiabatic index
     void* table_dev = nullptr;      // its records (library-owned)
     float* seed_params = nullptr;   // seed network parameters (device, MF_MLP_PARAMS)
     float* seed_grid = nullptr;     // its predictions on the (ln E, |M|/E) grid
@@ -69,8 +72,8 @@ struct mf_grid_s {
     int seg_override[3] = {0, 0, 0};
     int block = 256;
     unsigned long long* dstats = nullptr;  // (n_events + 1) * ST_WORDS; the last slot is scratch
-    double* dpartial = nullptr;            // kTotalsBlocks * 4
-    double* dtot = nullptr;                // n_events * 4
+    double* dpartial = nullptr;            // kTotalsBlocks * kMaxComp
+    double* dtot = nullptr;                // n_events * kMaxComp
     std::vector<void*> allocs;
     // kernel timing (mf_set_profiling)
     bool profiling = false;
@@ -212,13 +215,13 @@ void set_axis_const(AxisConst<T>& ac, double dt, double dx, double alpha, bool p
 // Argument block of one axis sweep d of one Runge-Kutta stage of event ev.
 // seg: cells per thread (y, z) or chunks of 64 row items per wavefront (x).
 template <typename T>
-SweepArgs<T> make_sweep_args(const Event& ev, int d, int seg, unsigned long long* stats, void* const uin[4],
-                             void* const u0[4], void* const out[4], int kind, double dt, bool want_smax)
+SweepArgs<T> make_sweep_args(const Event& ev, int d, int seg, unsigned long long* stats, void* const uin[],
+                             void* const u0[], void* const out[], int kind, double dt, bool want_smax)
 {
     const AxisGeom geo = axis_geom(ev.d.n, d);
     SweepArgs<T> a;
     std::memset(&a, 0, sizeof(a));
-    for (int c = 0; c < 4; c++) {
+    for (int c = 0; c < ev.nc; c++) {
         a.u[c] = (const T*)uin[c];
         a.L[c] = (T*)ev.L[c];
         a.u0[c] = (const T*)u0[c];
@@ -305,11 +308,24 @@ StageCtx stage_ctx(mf_grid_s* g)
     return c;
 }
 
+// Sweeps with the charge exist for FP64 with p = c e (a passive charge) and the ideal gas.
 template <typename T, class Eos>
-int run_stage(const StageCtx& cx, const Eos& eos, Event& ev, unsigned long long* stats, void* const uin[4],
-              void* const u0[4], void* const out[4], int kind, double dt, double ts, bool want_smax)
+constexpr bool kChargeSweeps = std::is_same<T, double>::value &&
+                               (std::is_same<Eos, EosIdeal<double>>::value || std::is_same<Eos, EosGamma>::value);
+
+template <typename T, class Eos>
+int run_stage(const StageCtx& cx, const Eos& eos, Event& ev, unsigned long long* stats, void* const uin[],
+              void* const u0[], void* const out[], int kind, double dt, double ts, bool want_smax)
 {
-    if (ev.DL) {  // unsplit Hancock ablation: the three-axis corrections of the stage input
+    if constexpr (!kChargeSweeps<T, Eos>) {
+        if (ev.nc == 5) return fail(MF_ERR_ARG, "the charge runs in FP64 with p = c e or the ideal gas");
+    }
+    if constexpr (std::is_same<Eos, EosGamma>::value) {
+        if (ev.nc != 5) return fail(MF_ERR_ARG, "the ideal gas needs the charge");
+    }
+    if constexpr (std::is_same<Eos, EosGamma>::value) {
+        if (ev.DL) return fail(MF_ERR_ARG, "the unsplit Hancock ablation carries no charge");
+    } else if (ev.DL) {  // unsplit Hancock ablation: the three-axis corrections of the stage input
         UnsplitArgs<T> ua;
         std::memset(&ua, 0, sizeof(ua));
         for (int c = 0; c < 4; c++) ua.u[c] = (const T*)uin[c];
@@ -326,10 +342,16 @@ int run_stage(const StageCtx& cx, const Eos& eos, Event& ev, unsigned long long*
     }
     for (int d = 0; d < 3; d++) {
         const AxisGeom geo = axis_geom(ev.d.n, d);
-        int seg = cx.seg_override[d] > 0
-                      ? cx.seg_override[d]
-                      : default_shape(ev, d, cx.table,
-                                      sweep_waves_per_simd<T, Eos>(d, ev.d.limiter, ev.jet && d == 2, cx.block));
+        int waves = 0;
+        if (cx.seg_override[d] <= 0) {
+            if constexpr (kChargeSweeps<T, Eos>) {
+                if (ev.nc == 5) waves = sweep_waves_per_simd_charge<Eos>(d, ev.d.limiter, cx.block);
+            }
+            if constexpr (!std::is_same<Eos, EosGamma>::value) {
+                if (ev.nc == 4) waves = sweep_waves_per_simd<T, Eos>(d, ev.d.limiter, ev.jet && d == 2, cx.block);
+            }
+        }
+        int seg = cx.seg_override[d] > 0 ? cx.seg_override[d] : default_shape(ev, d, cx.table, waves);
         if (d > 0) seg = std::min(seg, geo.N);
         SweepArgs<T> a = make_sweep_args<T>(ev, d, seg, stats, uin, u0, out, kind, dt, want_smax);
         const bool jet = ev.jet && d == 2;
@@ -348,8 +370,15 @@ int run_stage(const StageCtx& cx, const Eos& eos, Event& ev, unsigned long long*
             MF_HIP(cx.prof->take_event(&tm.stop));
             MF_HIP(hipEventRecord(tm.start, cx.stream));
         }
-        hipError_t e = ev.DL ? launch_sweep_unsplit<T, Eos>(d, ev.d.limiter, jet, grid, block, cx.stream, a, eos)
-                             : launch_sweep<T, Eos>(d, ev.d.limiter, jet, grid, block, cx.stream, a, eos);
+        hipError_t e = hipErrorInvalidValue;
+        if constexpr (kChargeSweeps<T, Eos>) {
+            if (ev.nc == 5) e = launch_sweep_charge<Eos>(d, ev.d.limiter, grid, block, cx.stream, a, eos);
+        }
+        if constexpr (!std::is_same<Eos, EosGamma>::value) {
+            if (ev.nc == 4)
+                e = ev.DL ? launch_sweep_unsplit<T, Eos>(d, ev.d.limiter, jet, grid, block, cx.stream, a, eos)
+                          : launch_sweep<T, Eos>(d, ev.d.limiter, jet, grid, block, cx.stream, a, eos);
+        }
         if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("sweep launch: ") + hipGetErrorString(e));
         if (cx.prof) {
             MF_HIP(hipEventRecord(tm.stop, cx.stream));
@@ -384,6 +413,7 @@ int run_steps(mf_grid_s* g, Event& ev, unsigned long long* stats, double dt, int
 {
     const StageCtx cx = stage_ctx(g);
     if (g->eos_kind == MF_EOS_TABLE) return run_steps_eos<double>(cx, g->table, ev, stats, dt, nsteps);
+    if (g->eos_kind == MF_EOS_GAMMA) return run_steps_eos<double>(cx, EosGamma::make(g->gamma), ev, stats, dt, nsteps);
     if (ev.d.dtype == MF_F32) return run_steps_eos<float>(cx, EosIdeal<float>::make(g->cs2), ev, stats, dt, nsteps);
     return run_steps_eos<double>(cx, EosIdeal<double>::make(g->cs2), ev, stats, dt, nsteps);
 }
@@ -420,16 +450,18 @@ void monotone_slopes(int n, const double* x, const double* y, std::vector<double
     m[n - 1] = end_slope(h[n - 2], h[n - 3], del[n - 2], del[n - 3]);
 }
 
-// Conservation sums of one event into out[4] (device); partial: 4 kTotalsBlocks doubles (device).
+// Conservation sums of one event's nc components into out[nc] (device); partial: kMaxComp
+// kTotalsBlocks doubles (device).
 template <typename T>
 int enqueue_totals(hipStream_t stream, double* partial, const Event& ev, double* out)
 {
     TotalsArgs<T> a;
-    for (int c = 0; c < 4; c++) a.U[c] = (const T*)ev.U[c];
+    std::memset(&a, 0, sizeof(a));
+    for (int c = 0; c < ev.nc; c++) a.U[c] = (const T*)ev.U[c];
     a.n = ev.ncell;
     a.partial = partial;
     const double dV = ev.d.dx[0] * ev.d.dx[1] * ev.d.dx[2];
-    hipError_t e = launch_totals<T>(stream, a, kTotalsBlocks, dV, out);
+    hipError_t e = launch_totals<T>(stream, a, ev.nc, kTotalsBlocks, dV, out);
     if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("totals launch: ") + hipGetErrorString(e));
     return MF_OK;
 }
@@ -440,7 +472,7 @@ int enqueue_totals_any(hipStream_t stream, double* partial, const Event& ev, dou
                                 : enqueue_totals<double>(stream, partial, ev, out);
 }
 
-// Host statistics of one event from its device counters w[ST_WORDS] and totals tot[4].
+// Host statistics of one event from its device counters w[ST_WORDS] and totals tot[0..3].
 void fill_stats(const Event& ev, const unsigned long long* w, const double* tot, double dt, mf_stats& s)
 {
     std::memset(&s, 0, sizeof(s));
@@ -760,8 +792,11 @@ int check_desc(const mf_grid_desc& d)
     if (d.musta_k < 1 || d.musta_k > 64) return fail(MF_ERR_ARG, "musta_k must be in [1, 64]");
     if (d.rk_order != 2 && d.rk_order != 3) return fail(MF_ERR_ARG, "rk_order must be 2 or 3");
     if (!(d.alpha > 0.0) || !std::isfinite(d.alpha)) return fail(MF_ERR_ARG, "alpha must be finite and > 0");
-    if (d.flags & ~(MF_FLAG_STRICT | MF_FLAG_PREDICTOR_ALPHA | MF_FLAG_UNSPLIT_HANCOCK))
+    if (d.flags & ~(MF_FLAG_STRICT | MF_FLAG_PREDICTOR_ALPHA | MF_FLAG_UNSPLIT_HANCOCK | MF_FLAG_CHARGE))
         return fail(MF_ERR_ARG, "unknown flag bits");
+    if ((d.flags & MF_FLAG_CHARGE) && d.dtype != MF_F64) return fail(MF_ERR_ARG, "the charge runs in FP64 only");
+    if ((d.flags & MF_FLAG_CHARGE) && (d.flags & MF_FLAG_UNSPLIT_HANCOCK))
+        return fail(MF_ERR_ARG, "the unsplit Hancock ablation carries no charge");
     return MF_OK;
 }
 
@@ -810,11 +845,15 @@ int mf_grid_init(mf_grid_t* out, const mf_grid_desc* descs, int32_t n_events, vo
     if (!out || !descs || !U_dev) return fail(MF_ERR_ARG, "null argument");
     *out = nullptr;
     if (n_events < 1) return fail(MF_ERR_ARG, "n_events must be >= 1");
+    const bool charge = (descs[0].flags & MF_FLAG_CHARGE) != 0;
+    const int nc = charge ? 5 : 4;
     for (int i = 0; i < n_events; i++) {
         int rc = check_desc(descs[i]);
         if (rc) return rc;
-        for (int c = 0; c < 4; c++)
-            if (!U_dev[4 * i + c]) return fail(MF_ERR_ARG, "null state pointer");
+        if (((descs[i].flags & MF_FLAG_CHARGE) != 0) != charge)
+            return fail(MF_ERR_ARG, "all events of a handle carry the charge or none does");
+        for (int c = 0; c < nc; c++)
+            if (!U_dev[(int64_t)nc * i + c]) return fail(MF_ERR_ARG, "null state pointer");
     }
     mf_grid_s* g = new (std::nothrow) mf_grid_s();
     if (!g) return fail(MF_ERR_NOMEM, "host allocation failed");
@@ -824,10 +863,11 @@ int mf_grid_init(mf_grid_t* out, const mf_grid_desc* descs, int32_t n_events, vo
     for (int i = 0; i < n_events && rc == MF_OK; i++) {
         Event& ev = g->ev[i];
         ev.d = descs[i];
+        ev.nc = nc;
         ev.ncell = (int64_t)ev.d.n[0] * ev.d.n[1] * ev.d.n[2];
         const size_t bytes = (size_t)ev.ncell * elem_size(ev.d.dtype);
-        for (int c = 0; c < 4 && rc == MF_OK; c++) {
-            ev.U[c] = U_dev[4 * i + c];
+        for (int c = 0; c < nc && rc == MF_OK; c++) {
+            ev.U[c] = U_dev[(int64_t)nc * i + c];
             rc = g->alloc(&ev.U1[c], bytes);
             if (rc == MF_OK) rc = g->alloc(&ev.L[c], bytes);
             if (rc == MF_OK && ev.d.rk_order == 3) rc = g->alloc(&ev.U2[c], bytes);
@@ -838,8 +878,8 @@ int mf_grid_init(mf_grid_t* out, const mf_grid_desc* descs, int32_t n_events, vo
         }
     }
     if (rc == MF_OK) rc = g->alloc((void**)&g->dstats, sizeof(unsigned long long) * ST_WORDS * (n_events + 1));
-    if (rc == MF_OK) rc = g->alloc((void**)&g->dpartial, sizeof(double) * 4 * kTotalsBlocks);
-    if (rc == MF_OK) rc = g->alloc((void**)&g->dtot, sizeof(double) * 4 * n_events);
+    if (rc == MF_OK) rc = g->alloc((void**)&g->dpartial, sizeof(double) * kMaxComp * kTotalsBlocks);
+    if (rc == MF_OK) rc = g->alloc((void**)&g->dtot, sizeof(double) * kMaxComp * n_events);
     if (rc != MF_OK) {
         std::string msg = g_err;
         delete g;
@@ -862,6 +902,7 @@ int mf_set_eos(mf_grid_t g, int32_t kind, double cs2, const double* e_tab, const
                const mf_surrogate* s)
 {
     if (!g) return fail(MF_ERR_ARG, "null handle");
+    const bool charge = g->ev[0].nc == 5;
     if (kind == MF_EOS_IDEAL) {
         if (!(cs2 > 0.0 && cs2 < 1.0)) return fail(MF_ERR_ARG, "cs2 must be in (0, 1)");
         if (s) return fail(MF_ERR_ARG, "a surrogate needs the table EoS");
@@ -869,7 +910,16 @@ int mf_set_eos(mf_grid_t g, int32_t kind, double cs2, const double* e_tab, const
         g->cs2 = cs2;
         return MF_OK;
     }
+    if (kind == MF_EOS_GAMMA) {  // cs2 carries the adiabatic index
+        if (!(cs2 >= 1.0 && cs2 <= 2.0)) return fail(MF_ERR_ARG, "the adiabatic index must be in [1, 2]");
+        if (!charge) return fail(MF_ERR_ARG, "the ideal gas needs the charge (MF_FLAG_CHARGE)");
+        if (s) return fail(MF_ERR_ARG, "a surrogate needs the table EoS");
+        g->eos_kind = MF_EOS_GAMMA;
+        g->gamma = cs2;
+        return MF_OK;
+    }
     if (kind != MF_EOS_TABLE) return fail(MF_ERR_ARG, "unknown EoS kind");
+    if (charge) return fail(MF_ERR_ARG, "the tabulated EoS carries no charge");
     if (!e_tab || !p_tab || n_tab < 3) return fail(MF_ERR_ARG, "table EoS needs n_tab >= 3 host nodes");
     for (const Event& ev : g->ev)
         if (ev.d.dtype != MF_F64) return fail(MF_ERR_ARG, "the table EoS runs in FP64 only");
@@ -943,6 +993,7 @@ int mf_set_source_jet(mf_grid_t g, int32_t event, const double x0[3], double v, 
     if (!(v > 0.0 && v < 1.0) || !(sigma > 0.0) || !std::isfinite(dEdx))
         return fail(MF_ERR_ARG, "jet needs 0 < v < 1, sigma > 0, finite dEdx");
     Event& ev = g->ev[event];
+    if (ev.nc == 5 && dEdx != 0.0) return fail(MF_ERR_ARG, "the jet source runs without the charge");
     ev.jet = dEdx != 0.0;
     for (int q = 0; q < 3; q++) ev.jet_x0[q] = x0[q];
     ev.jet_v = v;
@@ -1006,16 +1057,17 @@ static int collect_stats(mf_grid_t g, const double* dts, mf_stats* st)
 {
     const int ne = (int)g->ev.size();
     for (int i = 0; i < ne; i++) {
-        int rc = enqueue_totals_any(g->stream, g->dpartial, g->ev[i], g->dtot + 4 * i);
+        int rc = enqueue_totals_any(g->stream, g->dpartial, g->ev[i], g->dtot + (size_t)kMaxComp * i);
         if (rc) return rc;
     }
     std::vector<unsigned long long> hs((size_t)ST_WORDS * ne);
-    std::vector<double> ht((size_t)4 * ne);
+    std::vector<double> ht((size_t)kMaxComp * ne);
     MF_HIP(hipMemcpyAsync(hs.data(), g->dstats, hs.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                           g->stream));
     MF_HIP(hipMemcpyAsync(ht.data(), g->dtot, ht.size() * sizeof(double), hipMemcpyDeviceToHost, g->stream));
     MF_HIP(hipStreamSynchronize(g->stream));
-    for (int i = 0; i < ne; i++) fill_stats(g->ev[i], &hs[(size_t)ST_WORDS * i], &ht[4 * i], dts[i], st[i]);
+    for (int i = 0; i < ne; i++)
+        fill_stats(g->ev[i], &hs[(size_t)ST_WORDS * i], &ht[(size_t)kMaxComp * i], dts[i], st[i]);
     return MF_OK;
 }
 
@@ -1072,6 +1124,7 @@ int mf_batch_step(mf_grid_t g, const double* dt, int32_t nsteps, mf_stats* st)
             return fail(MF_ERR_ARG, "batched events must share dtype, limiter and rk_order");
         if (di.flags & MF_FLAG_UNSPLIT_HANCOCK)
             return fail(MF_ERR_ARG, "the unsplit Hancock ablation runs with mf_step only");
+        if (di.flags & MF_FLAG_CHARGE) return fail(MF_ERR_ARG, "events with the charge run with mf_step only");
     }
     int rc = ensure_batch_buffers(g);
     if (rc) return rc;
@@ -1105,7 +1158,7 @@ int mf_batch_step(mf_grid_t g, const double* dt, int32_t nsteps, mf_stats* st)
     return check_strict(g, st);
 }
 
-int mf_con2prim(mf_grid_t g, const void* const U[4], void* const prim[5], int64_t n, int32_t* iters_dev,
+int mf_con2prim(mf_grid_t g, const void* const U[], void* const prim[], int64_t n, int32_t* iters_dev,
                 int32_t mode)
 {
     if (!g || !U || !prim) return fail(MF_ERR_ARG, "null argument");
@@ -1117,14 +1170,22 @@ int mf_con2prim(mf_grid_t g, const void* const U[4], void* const prim[5], int64_
         return fail(MF_ERR_ARG, "seeded con2prim needs the table EoS");
     if (mode == MF_C2P_SEEDED && !g->has_seed) return fail(MF_ERR_ARG, "seeded con2prim needs a surrogate");
     if (n == 0) return MF_OK;
-    for (int c = 0; c < 4; c++)
+    const int nc = g->ev[0].nc;
+    for (int c = 0; c < nc; c++)
         if (!U[c]) return fail(MF_ERR_ARG, "null state pointer");
-    for (int c = 0; c < 5; c++)
+    for (int c = 0; c < nc + 1; c++)
         if (!prim[c]) return fail(MF_ERR_ARG, "null output pointer");
     unsigned long long* stats = g->dstats + (size_t)ST_WORDS * g->ev.size();
     hipError_t e = launch_fill_u64(g->stream, stats, ST_WORDS, 0ULL);
     if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("stats reset: ") + hipGetErrorString(e));
-    if (mode != MF_C2P_PLAIN) {
+    if (nc == 5) {  // with the charge: FP64, p = c e or the ideal gas
+        C2PArgs<double> a;
+        for (int c = 0; c < 5; c++) a.U[c] = (const double*)U[c];
+        for (int c = 0; c < 6; c++) a.prim[c] = (double*)prim[c];
+        a.iters = iters_dev; a.n = n; a.stats = stats;
+        if (g->eos_kind == MF_EOS_GAMMA) e = launch_con2prim_charge<EosGamma>(n, g->stream, a, EosGamma::make(g->gamma));
+        else e = launch_con2prim_charge<EosIdeal<double>>(n, g->stream, a, EosIdeal<double>::make(g->cs2));
+    } else if (mode != MF_C2P_PLAIN) {
         C2PArgs<double> a;
         for (int c = 0; c < 4; c++) a.U[c] = (const double*)U[c];
         for (int c = 0; c < 5; c++) a.prim[c] = (double*)prim[c];
@@ -1219,14 +1280,15 @@ int mf_mlp_adam(float* params, const float* grad, float* m, float* v, int32_t st
     return MF_OK;
 }
 
-int mf_totals(mf_grid_t g, int32_t event, double out[4])
+int mf_totals(mf_grid_t g, int32_t event, double* out)
 {
     if (!g || !out) return fail(MF_ERR_ARG, "null argument");
     if (event < 0 || event >= (int)g->ev.size()) return fail(MF_ERR_ARG, "event out of range");
     const Event& ev = g->ev[event];
-    int rc = enqueue_totals_any(g->stream, g->dpartial, ev, g->dtot + 4 * event);
+    double* dt = g->dtot + (size_t)kMaxComp * event;
+    int rc = enqueue_totals_any(g->stream, g->dpartial, ev, dt);
     if (rc) return rc;
-    MF_HIP(hipMemcpyAsync(out, g->dtot + 4 * event, 4 * sizeof(double), hipMemcpyDeviceToHost, g->stream));
+    MF_HIP(hipMemcpyAsync(out, dt, ev.nc * sizeof(double), hipMemcpyDeviceToHost, g->stream));
     MF_HIP(hipStreamSynchronize(g->stream));
     return MF_OK;
 }

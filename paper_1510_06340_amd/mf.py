@@ -18,13 +18,14 @@ MF_OK, MF_ERR_ARG, MF_ERR_NOMEM, MF_ERR_HIP, MF_ERR_STATE, MF_ERR_UNPHYSICAL, MF
 MF_BC_OUTFLOW, MF_BC_PERIODIC = 0, 1
 MF_F64, MF_F32 = 0, 1
 MF_LIM_NONE, MF_LIM_MINMOD, MF_LIM_SUPERBEE, MF_LIM_MC, MF_LIM_VANLEER, MF_LIM_VANALBADA = range(6)
-MF_EOS_IDEAL, MF_EOS_TABLE = 0, 1
+MF_EOS_IDEAL, MF_EOS_TABLE, MF_EOS_GAMMA = 0, 1, 2
 MF_C2P_PLAIN, MF_C2P_SEEDED, MF_C2P_CONFORMAL = 0, 1, 2
 MF_MLP_HIDDEN, MF_MLP_PARAMS = 64, 4417
 MF_MLP_NOALLOC_MAX_N = 16384
 MF_FLAG_STRICT = 1
 MF_FLAG_PREDICTOR_ALPHA = 2
 MF_FLAG_UNSPLIT_HANCOCK = 4
+MF_FLAG_CHARGE = 8
 
 EXPORTS = ["mf_grid_init", "mf_set_eos", "mf_set_source_jet", "mf_set_time", "mf_step", "mf_batch_step",
            "mf_con2prim", "mf_con2prim_stats", "mf_totals", "mf_set_tuning", "mf_set_profiling", "mf_get_profile",
@@ -127,6 +128,8 @@ def make_desc(n, dx, origin, bc, dtype=MF_F64, limiter=MF_LIM_MC, k=3, rk=2, alp
 
 
 def desc_from_workload(w, dtype=MF_F64, flags=0) -> GridDesc:
+    if w.extra.get("charge"):
+        flags |= MF_FLAG_CHARGE
     return make_desc(w.n, w.dx, w.xlo, w.bc, dtype, w.limiter, w.k, w.rk, w.alpha, flags)
 
 
@@ -134,7 +137,8 @@ class Grid:
     """A handle over one or more events whose state lives in caller-owned device tensors.
 
     states: list (one per event) of 4 contiguous CUDA tensors (E, Mx, My, Mz),
-    each with n[0]*n[1]*n[2] elements of the event's dtype.
+    each with n[0]*n[1]*n[2] elements of the event's dtype; 5 (R last) for
+    descriptors with MF_FLAG_CHARGE.
     """
 
     def __init__(self, descs, states, stream=None):
@@ -149,12 +153,13 @@ class Grid:
         for d, s in zip(self.descs, self.states):
             want = torch.float32 if d.dtype == MF_F32 else torch.float64
             ncell = d.n[0] * d.n[1] * d.n[2]
-            if len(s) != 4:
-                raise ValueError("4 component tensors per event")
+            if len(s) != (5 if d.flags & MF_FLAG_CHARGE else 4):
+                raise ValueError("4 component tensors per event (5 with the charge)")
             for t in s:
                 if not t.is_cuda or t.dtype != want or not t.is_contiguous() or t.numel() != ncell:
                     raise ValueError("state tensors must be contiguous CUDA tensors of the event's dtype and size")
-        arr = (C.c_void_p * (4 * len(self.descs)))(*[_ptr(t) for s in self.states for t in s])
+        ptrs = [_ptr(t) for s in self.states for t in s]
+        arr = (C.c_void_p * len(ptrs))(*ptrs)
         darr = (GridDesc * len(self.descs))(*self.descs)
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -169,6 +174,10 @@ class Grid:
 
     def set_eos_ideal(self, cs2=1.0 / 3.0):
         _check(lib().mf_set_eos(self.h, MF_EOS_IDEAL, float(cs2), None, None, 0, None))
+
+    def set_eos_gamma(self, gamma=5.0 / 3.0):
+        """The ideal gas p = (gamma - 1) max(e - n, 0) (needs the charge)."""
+        _check(lib().mf_set_eos(self.h, MF_EOS_GAMMA, float(gamma), None, None, 0, None))
 
     def set_eos_table(self, e, p, surrogate=None):
         """surrogate: None or a SeedNetwork (keeps its arrays alive)."""
@@ -210,10 +219,11 @@ class Grid:
         return None
 
     def con2prim(self, U, prim, iters=None, mode=MF_C2P_PLAIN):
-        """U: 4 device tensors, prim: 5 device tensors (e, p, vx, vy, vz), iters: int32 tensor or None."""
+        """U: 4 device tensors, prim: 5 device tensors (e, p, vx, vy, vz), iters: int32 tensor or None;
+        with the charge U: 5 (R last), prim: 6 (n last)."""
         n = U[0].numel()
-        u = (C.c_void_p * 4)(*[_ptr(t) for t in U])
-        p = (C.c_void_p * 5)(*[_ptr(t) for t in prim])
+        u = (C.c_void_p * len(U))(*[_ptr(t) for t in U])
+        p = (C.c_void_p * len(prim))(*[_ptr(t) for t in prim])
         it = C.c_void_p(_ptr(iters)) if iters is not None else None
         _check(lib().mf_con2prim(self.h, u, p, n, it, int(mode)))
 
@@ -234,7 +244,9 @@ class Grid:
         return list(out)
 
     def totals(self, event=0):
-        out = (C.c_double * 4)()
+        """Sums of E, Mx, My, Mz (and R with the charge) times the cell volume."""
+        nc = 5 if self.descs[event].flags & MF_FLAG_CHARGE else 4
+        out = (C.c_double * nc)()
         _check(lib().mf_totals(self.h, int(event), out))
         return list(out)
 

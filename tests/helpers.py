@@ -5,10 +5,11 @@ from paper_1510_06340_amd import mf
 
 
 def to_dev(U, dtype="f64"):
-    """numpy (4, nz, ny, nx) -> list of 4 contiguous CUDA tensors (flattened)."""
+    """numpy (nc, nz, ny, nx) -> list of nc contiguous CUDA tensors (flattened); nc = 4, or 5 with the charge."""
     import torch
     tdt = torch.float64 if dtype == "f64" else torch.float32
-    return [torch.from_numpy(np.ascontiguousarray(U[c]).ravel()).to(device="cuda", dtype=tdt) for c in range(4)]
+    return [torch.from_numpy(np.ascontiguousarray(U[c]).ravel()).to(device="cuda", dtype=tdt)
+            for c in range(U.shape[0])]
 
 
 def from_dev(ts, shape):
@@ -26,13 +27,16 @@ def rel_l1_E(Ug, Uo):
 
 
 def gpu_run(w, U, dtype="f64", nsteps=None, jet_x0=None, eos_table=None, flags=0, tuning=None, t0=0.0):
-    """Run the HIP path on workload w from state U; returns (U_new numpy FP64, stats of event 0)."""
+    """Run the HIP path on workload w from state U; returns (U_new numpy FP64, stats of event 0).
+    With w.extra["charge"] the state carries R (5 components); w.extra["gamma"] selects the ideal gas."""
     import torch
     dev = to_dev(U, dtype)
     d = mf.desc_from_workload(w, mf.MF_F32 if dtype == "f32" else mf.MF_F64, flags)
     g = mf.Grid([d], [dev])
     try:
-        if eos_table is None:
+        if w.extra.get("gamma") is not None:
+            g.set_eos_gamma(w.extra["gamma"])
+        elif eos_table is None:
             g.set_eos_ideal(w.cs2)
         else:
             g.set_eos_table(*eos_table)

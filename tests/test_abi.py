@@ -63,7 +63,7 @@ def _init(lib, desc, ptrs=None):
 @pytest.mark.parametrize("field,value", [
     ("n", (0, 4, 4)), ("n", (65536, 65536, 2)), ("dx", (0.1, 0.0, 0.1)), ("dx", (0.1, float("nan"), 0.1)),
     ("bc", (0, 2, 0)), ("origin", (0.0, float("inf"), 0.0)), ("dtype", 7), ("limiter", 9), ("musta_k", 0),
-    ("musta_k", 65), ("rk_order", 4), ("alpha", -1.0), ("flags", 8)])
+    ("musta_k", 65), ("rk_order", 4), ("alpha", -1.0), ("flags", 16)])
 def test_invalid_descriptors_are_rejected(lib, field, value):
     d = mf.make_desc((4, 4, 4), (0.1, 0.1, 0.1), (0, 0, 0), (0, 0, 0))
     if isinstance(value, tuple):
@@ -73,6 +73,25 @@ def test_invalid_descriptors_are_rejected(lib, field, value):
     rc, h = _init(lib, d)
     assert rc == mf.MF_ERR_ARG and not h.value
     assert len(mf.last_error()) > 0
+
+
+def test_charge_descriptors_are_checked(lib):
+    """MF_FLAG_CHARGE: five pointers per event, FP64 only, not with the unsplit ablation, and all
+    events of a handle alike (checked before any device work)."""
+    h = C.c_void_p()
+    d = mf.make_desc((4, 4, 4), (0.1, 0.1, 0.1), (0, 0, 0), (0, 0, 0), flags=mf.MF_FLAG_CHARGE)
+    arr5 = (C.c_void_p * 5)(1, 2, 3, 4, 0)
+    assert lib.mf_grid_init(C.byref(h), C.byref(d), 1, arr5, None) == mf.MF_ERR_ARG
+    assert "null state pointer" in mf.last_error()
+    arr5 = (C.c_void_p * 5)(1, 2, 3, 4, 5)
+    for bad in (dict(dtype=mf.MF_F32), dict(flags=mf.MF_FLAG_CHARGE | mf.MF_FLAG_UNSPLIT_HANCOCK)):
+        db = mf.make_desc((4, 4, 4), (0.1, 0.1, 0.1), (0, 0, 0), (0, 0, 0), **dict(dict(flags=mf.MF_FLAG_CHARGE), **bad))
+        assert lib.mf_grid_init(C.byref(h), C.byref(db), 1, arr5, None) == mf.MF_ERR_ARG
+        assert not h.value
+    two = (mf.GridDesc * 2)(d, mf.make_desc((4, 4, 4), (0.1, 0.1, 0.1), (0, 0, 0), (0, 0, 0)))
+    arr10 = (C.c_void_p * 10)(*range(1, 11))
+    assert lib.mf_grid_init(C.byref(h), two, 2, arr10, None) == mf.MF_ERR_ARG
+    assert "charge" in mf.last_error()
 
 
 def test_no_events_is_rejected(lib):
