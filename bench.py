@@ -12,11 +12,19 @@ Prints one JSON line.  `roofline` is for the axis-sweep kernel (the only kernel
 in the step), from HIP events around every sweep launch on the library's stream.
 `cpu_baseline` times the FP64 CPU oracle on the host cores on the first steps of
 the same workload.
+
+The default line also carries `batched_vs_plain`: a few timed steps of the
+64-event ensemble (one persistent launch per sweep over all events, replayed
+from a HIP graph, against one mf_step call per event) and of the 32 x 192^3
+crossover workload under the tabulated EoS (batched plain, batched with the
+learned ln e seed trained in the run, and per-event plain), each with its own
+whole-step roofline (Newton iterations counted) and a bounded oracle sample.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -41,13 +49,23 @@ C2P_FLUX = 22   # ideal-EoS con2prim + physical flux along one axis (energy flux
 LIMITER_OPS = {0: 2, 1: 1, 2: 5, 3: 5, 4: 4, 5: 7}   # MC computes phi / 2 directly (below)
 
 
-def flops_per_cell_axis(k: int, limiter: int) -> int:
+# Tabulated EoS: con2prim + flux along one axis without Newton iterations: |M|^2 (5), the
+# bracket [E - |M|^2/E, E] and its midpoint (4), one piece lookup of p and dp/de (the
+# piece's t (2), the cubic (6), its derivative (7) and the piece index (1)), then
+# v = M / (E + p) and the momentum fluxes (11).
+C2P_FLUX_TABLE = 5 + 4 + 16 + 11
+# One safeguarded Newton iteration: g and g' (9), the step and its acceptance test (6),
+# the bracket update (3) and the lookup at the new iterate (16).
+NEWTON_ITER_FLOPS = 34
+
+
+def flops_per_cell_axis(k: int, limiter: int, c2p_flux: int = C2P_FLUX) -> int:
     """Reconstruction + Hancock half step + k-stage MUSTA-FORCE + flux difference, per cell and axis."""
     # 2 differences, the limiter, phi / 2 (folded into MC's terms) and the two face values
     recon = 4 * (2 + LIMITER_OPS[limiter] + (0 if limiter == 3 else 1) + 2)
-    hancock = 2 * C2P_FLUX + 4 * 4
+    hancock = 2 * c2p_flux + 4 * 4
     # per stage: Richtmyer state (5 per component) and F_lw + F_lf (6), then the predictor (6)
-    musta = k * (3 * C2P_FLUX + 4 * 11) + (k - 1) * 4 * 6
+    musta = k * (3 * c2p_flux + 4 * 11) + (k - 1) * 4 * 6
     return recon + hancock + musta + 4 * 2
 
 
@@ -127,8 +145,9 @@ def run_single(args, w, U, table=None, jet_x0=None):
     return ms_total, kms, klaunch, st
 
 
-def run_events(args, ws, Us, batched, table=None, seed_net=None):
-    """Many events: one batched handle (mf_batch_step) or one mf_step call per event in turn."""
+def run_events(ws, Us, batched, steps, warmup, table=None, seed_net=None):
+    """Many events: one batched handle (mf_batch_step) or one mf_step call per event in turn.
+    Returns (ms over the timed steps, per-event stats of one more step)."""
     import torch
     from paper_1510_06340_amd import mf
     devs = [upload(U, torch.float64) for U in Us]
@@ -157,12 +176,12 @@ def run_events(args, ws, Us, batched, table=None, seed_net=None):
             for h, dt in zip(per, dts):
                 h.step(dt, n, stats=False)
 
-    advance(max(args.warmup, 1))  # includes the autotuner and graph capture for the batched form
+    advance(max(warmup, 1))  # includes the autotuner and graph capture for the batched form
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
-    advance(args.steps)
+    advance(steps)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
@@ -171,7 +190,103 @@ def run_events(args, ws, Us, batched, table=None, seed_net=None):
         h.free()
     if g is not None:
         g.free()
+    del devs
+    torch.cuda.empty_cache()
     return ms, st
+
+
+def cpu_baseline_events(ws, Us, budget_s, table=None, crop=None):
+    """The oracle on event 0 (or on a central crop^3 block of it, outflow at the block's faces),
+    one step at a time until the budget is spent."""
+    import oracle
+    w, U = ws[0], Us[0]
+    what = f"event 0 ({w.n[0]}x{w.n[1]}x{w.n[2]})"
+    if crop is not None:
+        import copy
+        lo = [(w.n[d] - crop) // 2 for d in range(3)]
+        U = U[:, lo[2]:lo[2] + crop, lo[1]:lo[1] + crop, lo[0]:lo[0] + crop].copy()
+        w = copy.copy(w)
+        w.xlo = tuple(w.xlo[d] + lo[d] * w.dx[d] for d in range(3))
+        w.n = (crop, crop, crop)
+        what = f"the central {crop}^3 block of event 0 (outflow at its faces; the hot spots lie there)"
+    prob = oracle.Problem.from_workload(w, table=table)
+    steps, t_total, V = 0, 0.0, U
+    while steps < 20:
+        t0 = time.perf_counter()
+        V, _ = oracle.step(prob, V, w.dt, 1, steps * w.dt)
+        t_total += time.perf_counter() - t0
+        steps += 1
+        if t_total >= budget_s:
+            break
+    return {"value": w.cells * steps / t_total, "unit": "cell-updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"first {steps} RK2 step(s) of {what}, FP64 C oracle"
+                      f"{' (bisection con2prim on the table)' if table is not None else ''}, {t_total:.1f} s"}
+
+
+def event_compare(I, kind, steps, warmup, n_events=None, cpu_budget=0.0):
+    """Batched vs per-event throughput of the ensemble (64 uneven events, p = e/3) or of the
+    crossover workload (32 x 192^3, tabulated EoS; batched plain, batched with the learned
+    ln e seed, per-event plain).  Returns a dict (one block of the JSON line)."""
+    if kind == "ensemble":
+        ws = I.ensemble_workloads(n_events=n_events or 64)
+        table = None
+        desc = (f"ensemble: {len(ws)} events, sizes per axis from {{96..192}}, hot spots (seeds 1000+j), MC, k=3, "
+                "RK2, dt=0.03, p=e/3")
+    else:
+        ws = I.crossover_workloads(n_events=n_events or 32)
+        table = I.crossover_table()
+        desc = (f"crossover: {len(ws)} events of 192^3 (seeds 2000+j), tabulated crossover EoS, MC, k=3, RK2, "
+                "dt=0.03")
+    Us = [I.initial_state(w) for w in ws]
+    cells = sum(w.cells for w in ws)
+    k, lim = ws[0].k, ws[0].limiter
+    c2p = C2P_FLUX if table is None else C2P_FLUX_TABLE
+    fl_step = 3 * 2 * flops_per_cell_axis(k, lim, c2p) * cells   # 3 axes x 2 RK stages
+
+    def form(ms, st, extra=None):
+        iters = sum(x["newton_iters"] for x in st)   # of the one step after the timed ones
+        fl = fl_step + NEWTON_ITER_FLOPS * iters
+        achieved = fl * steps / (ms / 1e3) / 1e12
+        d = {"value": cells * steps / (ms / 1e3), "ms_per_step": ms / steps,
+             "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                          "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                          "flops_per_step": fl, "newton_iters_per_step": iters}}
+        if extra:
+            d.update(extra)
+        return d
+
+    out = {"workload": desc, "cells": cells, "steps": steps, "warmup": max(warmup, 1),
+           "note": (f"{steps} timed steps of the workload's {ws[0].steps}; whole-step times (graph replay "
+                    "has no per-launch events); Newton iterations per step measured on the step after the "
+                    "timed ones and counted at " + str(NEWTON_ITER_FLOPS) + " flops each")}
+    ms_b, st_b = run_events(ws, Us, True, steps, warmup, table)
+    out["batched"] = form(ms_b, st_b)
+    ms_p, st_p = run_events(ws, Us, False, steps, warmup, table)
+    out["per_event"] = form(ms_p, st_p)
+    out["speedup_batched_vs_per_event"] = out["batched"]["value"] / out["per_event"]["value"]
+    if kind == "crossover":
+        from paper_1510_06340_amd import surrogate
+        t0 = time.perf_counter()
+        E, M = surrogate.collect_states(n_samples=1 << 22, seed=42, n=128)
+        e, pr = surrogate.label_states(E, M, table)
+        t_collect = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        net = surrogate.train(E, M, e, pr, epochs=30, output=0)
+        t_train = time.perf_counter() - t0
+        err = surrogate.relative_error(net, E, M, e)
+        del E, M, e, pr
+        ms_s, st_s = run_events(ws, Us, True, steps, warmup, table, seed_net=net.network())
+        out["batched_seeded"] = form(ms_s, st_s, {
+            "seeds_outside_bracket_per_step": sum(x["n_fallback"] for x in st_s),
+            "seed": {"output": "ln e", "states": 1 << 22, "epochs": 30, "collect_label_s": t_collect,
+                     "train_s": t_train, "val_loss": net.history[-1][2],
+                     "rel_err_median": float(err.median()), "rel_err_p99": float(err.quantile(0.99))}})
+        out["seeded_vs_per_event_plain"] = out["batched_seeded"]["value"] / out["per_event"]["value"]
+        out["seeded_vs_batched_plain"] = out["batched_seeded"]["value"] / out["batched"]["value"]
+    if cpu_budget > 0:
+        out["cpu_baseline"] = cpu_baseline_events(ws, Us, cpu_budget, table, crop=64 if table is not None else None)
+    return out
 
 
 def calibration_copy(args):
@@ -190,7 +305,9 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's own count)")
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["hotspot", "shock", "jet", "ensemble", "crossover"], default="hotspot")
+    ap.add_argument("--workload", choices=["hotspot", "shock", "jet", "ensemble", "crossover", "seed"],
+                    default="hotspot",
+                    help="seed: the learned seed's kernels alone (network forward, gradient, Adam, seeded con2prim)")
     ap.add_argument("--n", type=int, default=None, help="cells per axis (hotspot / jet)")
     ap.add_argument("--events", type=int, default=None, help="events (ensemble / crossover)")
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
@@ -202,6 +319,9 @@ def main(argv=None):
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before timing, copy this many MiB device-to-device (a kernel of known traffic "
                          "for scaling hardware byte counters)")
+    ap.add_argument("--compare-steps", type=int, default=5,
+                    help="hotspot line: timed steps of the batched-vs-per-event and learned-seed comparisons "
+                         "(ensemble and crossover workloads) carried in the same JSON line; 0 = leave them out")
     ap.add_argument("--unsplit-hancock", action="store_true",
                     help="hotspot / shock: the unsplit Hancock reading (one correction per cell from all three "
                          "axes, computed by a pre-pass each stage) instead of the per-axis half step")
@@ -225,6 +345,8 @@ def main(argv=None):
     peak = FP64_PEAK_TFLOPS if args.dtype == "f64" else FP32_PEAK_TFLOPS
     if args.workload in ("ensemble", "crossover"):
         return bench_events(args, I)
+    if args.workload == "seed":
+        return bench_seed(args, I)
 
     table = None
     jet_x0 = None
@@ -257,10 +379,20 @@ def main(argv=None):
     ms_total, kms, klaunch, st = run_single(args, w, U, table, jet_x0)
 
     value = w.cells * args.steps / (ms_total / 1e3)
-    fl_axis = flops_per_cell_axis(w.k, w.limiter)
     n_launch = sum(klaunch)
     avg_launch_ms = sum(kms) / max(n_launch, 1)
-    achieved_tflops = fl_axis * w.cells / (avg_launch_ms / 1e3) / 1e12
+    if table is None:
+        fl_axis = flops_per_cell_axis(w.k, w.limiter)
+        if args.unsplit_hancock:
+            # the sweeps add the pre-pass's correction to both faces (8) instead of the per-axis
+            # Hancock half step (two flux evaluations and 16); the pre-pass is timed apart
+            fl_axis = fl_axis - (2 * C2P_FLUX + 4 * 4) + 8
+        fl_launch = fl_axis * w.cells
+    else:
+        # Newton iterations per sweep launch: those of the step after the timed ones, over its 6 sweeps
+        fl_axis = flops_per_cell_axis(w.k, w.limiter, C2P_FLUX_TABLE)
+        fl_launch = fl_axis * w.cells + NEWTON_ITER_FLOPS * st["newton_iters"] / (3 * w.rk)
+    achieved_tflops = fl_launch / (avg_launch_ms / 1e3) / 1e12
     hbm_bytes = bytes_per_cell_step(w.rk, elem)
     hbm_gbs = value * hbm_bytes / 1e9
     out = {
@@ -303,75 +435,132 @@ def main(argv=None):
     if args.unsplit_hancock:
         out["roofline"]["prepass_and_gaps_ms_per_step"] = (ms_total - sum(kms)) / args.steps
     if table is not None:
-        out["roofline"]["note"] = ("algorithmic flops counted as for p = e/3; the table lookups and Newton "
-                                   "iterations of the tabulated EoS are not counted")
+        out["roofline"]["newton_iters_per_step"] = st["newton_iters"]
+        out["roofline"]["note"] = (f"tabulated EoS: {C2P_FLUX_TABLE} flops per con2prim + flux (bracket, one "
+                                   f"piece lookup of p and dp/de, velocity, fluxes) and {NEWTON_ITER_FLOPS} per "
+                                   "Newton iteration, iterations measured on the step after the timed ones")
     if args.cpu_budget > 0 and args.workload != "jet":
         out["cpu_baseline"] = cpu_baseline(w, U, args.cpu_budget, table)
+    if (args.compare_steps > 0 and args.workload == "hotspot" and table is None and args.dtype == "f64"
+            and w.n == (256, 256, 256) and not args.unsplit_hancock):
+        del U
+        budget = min(args.cpu_budget, 4.0)
+        out["batched_vs_plain"] = {kind: event_compare(I, kind, args.compare_steps, 1, cpu_budget=budget)
+                                   for kind in ("ensemble", "crossover")}
     print(json.dumps(out), flush=True)
     return 0
 
 
 def bench_events(args, I):
-    """Ensemble (64 uneven events, p = e/3) or crossover (32 x 192^3, tabulated EoS): batched vs per-event."""
-    if args.workload == "ensemble":
-        ws = I.ensemble_workloads(n_events=args.events or 64)
-        table = None
-        desc = "ensemble: 64 events, sizes per axis from {96..192}, hot spots (seeds 1000+j), MC, k=3, RK2, dt=0.03"
-    else:
-        ws = I.crossover_workloads(n_events=args.events or 32)
-        table = I.crossover_table()
-        desc = "crossover: 32 events of 192^3 (seeds 2000+j), tabulated crossover EoS, MC, k=3, RK2, dt=0.03"
-    if args.steps is None:
-        args.steps = ws[0].steps
-    Us = [I.initial_state(w) for w in ws]
-    cells = sum(w.cells for w in ws)
-    seeded = None
-    if args.workload == "crossover":
-        import time
-        from paper_1510_06340_amd import surrogate
-        t0 = time.perf_counter()
-        E, M = surrogate.collect_states(n_samples=1 << 22, seed=42, n=128)
-        e, pr = surrogate.label_states(E, M, table)
-        seeded = {"collect_label_seconds": time.perf_counter() - t0}
-        for name, output in (("ln_e", 0), ("bracket_fraction", 1)):
-            t0 = time.perf_counter()
-            net = surrogate.train(E, M, e, pr, epochs=30, output=output)
-            err = surrogate.relative_error(net, E, M, e)
-            train_s = time.perf_counter() - t0
-            ms_s, st_s = run_events(args, ws, Us, batched=True, table=table, seed_net=net.network())
-            seeded[name] = {"value": cells * args.steps / (ms_s / 1e3), "ms_per_step": ms_s / args.steps,
-                            "newton_iters": sum(s["newton_iters"] for s in st_s),
-                            "guesses_outside_bracket": sum(s["n_fallback"] for s in st_s),
-                            "train": {"states": int(E.numel()), "epochs": 30, "seconds": train_s,
-                                      "val_loss": net.history[-1][2], "seed_rel_err_median": float(err.median()),
-                                      "seed_rel_err_p99": float(err.quantile(0.99))}}
-    ms_b, st_b = run_events(args, ws, Us, batched=True, table=table)
-    ms_p, st_p = run_events(args, ws, Us, batched=False, table=table)
-    value = cells * args.steps / (ms_b / 1e3)
-    plain = cells * args.steps / (ms_p / 1e3)
-    fl_axis = flops_per_cell_axis(ws[0].k, ws[0].limiter)
-    achieved = 3 * 2 * fl_axis * cells * args.steps / (ms_b / 1e3) / 1e12
+    """--workload ensemble | crossover: the line's value is the configured batched form (the
+    crossover workload's with the learned seed), with the other forms beside it."""
+    steps = args.steps if args.steps is not None else 10
+    blk = event_compare(I, args.workload, steps, args.warmup, args.events, args.cpu_budget)
+    main_form = blk["batched_seeded"] if args.workload == "crossover" else blk["batched"]
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": main_form["value"],
         "unit": "cell-updates/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_b / args.steps,
+        "steps": steps,
+        "warmup": blk["warmup"],
+        "ms_per_step": main_form["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "cells": cells, "form": "batched (persistent tile queue, graph replay)"},
-        "plain_per_event": {"value": plain, "ms_per_step": ms_p / args.steps, "speedup_batched": value / plain},
-        "batched_seeded": seeded,
-        "roofline": {"kernel": "k_batch_sweep (all sweeps of the step)", "bound": "alu", "achieved": achieved,
-                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": None, "note": "whole-step average (graph replay, no per-launch events)"},
-        "end_state": {"n_floor": sum(s["n_floor"] for s in st_b), "n_bad": sum(s["n_bad"] for s in st_b),
-                      "newton_iters": sum(s["newton_iters"] for s in st_b)},
+        "config": {"workload": blk["workload"], "cells": blk["cells"],
+                   "form": "batched (persistent tile queue, graph replay)"
+                           + (" with the learned ln e seed" if args.workload == "crossover" else "")},
+        "roofline": dict(main_form["roofline"], kernel="k_batch_sweep (all sweeps of the step)"),
+        "forms": blk,
+    }
+    if "cpu_baseline" in blk:
+        out["cpu_baseline"] = blk["cpu_baseline"]
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_seed(args, I):
+    """The seed network's kernels on their own: forward over 2^20 states, one epoch of
+    gradients and Adam steps at the training batch (4096), and con2prim of 2^20 crossover
+    states plain and seeded (network per state).  Network: Glorot initialisation (the
+    arithmetic per sample does not depend on the weights)."""
+    import torch
+    from paper_1510_06340_amd import mf, surrogate
+    reps = args.steps or 20
+    n = 1 << 20
+    batch = 4096
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    P = torch.from_numpy(surrogate.init_params(0)).cuda()
+    X = torch.randn((n, 2), generator=gen, device="cuda")
+    T = torch.randn(n, generator=gen, device="cuda")
+    y = torch.empty(n, device="cuda")
+    grad, loss = torch.zeros_like(P), torch.zeros(1, device="cuda")
+    m, v = torch.zeros_like(P), torch.zeros_like(P)
+    work = torch.empty(mf.mlp_workspace(batch), device="cuda")
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    ms_fwd = timed(lambda: mf.mlp_forward(P, X, y), reps)
+
+    def epoch():
+        for b in range(n // batch):
+            mf.mlp_grad(P, X[b * batch:(b + 1) * batch], T[b * batch:(b + 1) * batch], grad, loss, work)
+            mf.mlp_adam(P, grad, m, v, b + 1, 1e-3)
+
+    ms_epoch = timed(epoch, max(1, reps // 10))
+    ms_adam = timed(lambda: mf.mlp_adam(P, grad, m, v, 1, 1e-3), reps)
+    # crossover states: E log-uniform in [1e-2, 1e2], |M|/E uniform in [0, 0.99)
+    E = torch.exp(torch.empty(n, dtype=torch.float64, device="cuda").uniform_(math.log(1e-2), math.log(1e2),
+                                                                              generator=gen))
+    Ma = E * torch.empty(n, dtype=torch.float64, device="cuda").uniform_(0.0, 0.99, generator=gen)
+    U = [E, Ma, torch.zeros_like(E), torch.zeros_like(E)]
+    prim = [torch.empty_like(E) for _ in range(5)]
+    g = mf.Grid([mf.make_desc((n, 1, 1), (1, 1, 1), (0, 0, 0), (0, 0, 0))], [U])
+    net = mf.SeedNetwork(P.cpu().numpy(), (0.0, 0.0), (1.0, 1.0), 0.0, 1.0, 0)
+    g.set_eos_table(*I.crossover_table(), surrogate=net)
+    ms_plain = timed(lambda: g.con2prim(U, prim, None, mf.MF_C2P_PLAIN), reps)
+    ms_seeded = timed(lambda: g.con2prim(U, prim, None, mf.MF_C2P_SEEDED), reps)
+    g.free()
+    H = mf.MF_MLP_HIDDEN
+    mm_flops = 2 * H * H   # layer 2 per sample, on the matrix cores
+    fwd = n / (ms_fwd / 1e3)
+    out = {
+        "metric": "seed-network samples/s (forward)",
+        "value": fwd,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": reps,
+        "warmup": 1,
+        "ms_per_step": ms_fwd,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16 (FP32 accumulation)",
+        "data": "synthetic",
+        "config": {"workload": "seed network 2-64-64-1 tanh: forward of 2^20 states, one epoch of 256 "
+                               "gradient + Adam steps at batch 4096, con2prim of 2^20 crossover states"},
+        "forward": {"ms": ms_fwd, "samples_per_s": fwd, "layer2_mfma_TFLOPs": mm_flops * fwd / 1e12},
+        "train_epoch": {"ms": ms_epoch, "samples_per_s": n / (ms_epoch / 1e3),
+                        "layer2_mfma_TFLOPs": 3 * mm_flops * n / (ms_epoch / 1e3) / 1e12},
+        "adam_ms": ms_adam,
+        "con2prim": {"plain_ms": ms_plain, "seeded_ms": ms_seeded, "states": n},
+        "roofline": {"bound": "mfma", "kernel": "k_mlp_forward", "achieved": mm_flops * fwd / 1e12,
+                     "peak": 2500.0, "unit": "TFLOP/s", "frac": mm_flops * fwd / 1e12 / 2500.0, "traffic": None,
+                     "note": "layer-2 matrix flops against the dense BF16 matrix peak; the kernel's time goes to "
+                             "the 128 tanh per sample on the vector ALUs"},
     }
     print(json.dumps(out), flush=True)
     return 0
