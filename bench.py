@@ -57,16 +57,22 @@ C2P_FLUX_TABLE = 5 + 4 + 16 + 11
 # One safeguarded Newton iteration: g and g' (9), the step and its acceptance test (6),
 # the bracket update (3) and the lookup at the new iterate (16).
 NEWTON_ITER_FLOPS = 34
+# Ideal gas p = (gamma - 1)(e - n) with the charge: |M|^2 (5), the residual f(p), f'(p) at p = 0
+# (1 / (E + p), v^2, sqrt(1 - v^2), e, f, f': 18) and the start (1), then v_d and the five fluxes (7).
+C2P_FLUX_GAS = 5 + 18 + 1 + 7
+# One safeguarded Newton iteration on f(p): the residual (18), the step (2), its test (2) and the bracket (2).
+NEWTON_ITER_FLOPS_GAS = 24
 
 
-def flops_per_cell_axis(k: int, limiter: int, c2p_flux: int = C2P_FLUX) -> int:
-    """Reconstruction + Hancock half step + k-stage MUSTA-FORCE + flux difference, per cell and axis."""
+def flops_per_cell_axis(k: int, limiter: int, c2p_flux: int = C2P_FLUX, nc: int = 4) -> int:
+    """Reconstruction + Hancock half step + k-stage MUSTA-FORCE + flux difference, per cell and axis
+    (nc conserved components: 4, or 5 with the charge)."""
     # 2 differences, the limiter, phi / 2 (folded into MC's terms) and the two face values
-    recon = 4 * (2 + LIMITER_OPS[limiter] + (0 if limiter == 3 else 1) + 2)
-    hancock = 2 * c2p_flux + 4 * 4
+    recon = nc * (2 + LIMITER_OPS[limiter] + (0 if limiter == 3 else 1) + 2)
+    hancock = 2 * c2p_flux + nc * 4
     # per stage: Richtmyer state (5 per component) and F_lw + F_lf (6), then the predictor (6)
-    musta = k * (3 * c2p_flux + 4 * 11) + (k - 1) * 4 * 6
-    return recon + hancock + musta + 4 * 2
+    musta = k * (3 * c2p_flux + nc * 11) + (k - 1) * nc * 6
+    return recon + hancock + musta + nc * 2
 
 
 def flops_per_cell_stage(k: int, limiter: int) -> int:
@@ -74,10 +80,11 @@ def flops_per_cell_stage(k: int, limiter: int) -> int:
     return 3 * flops_per_cell_axis(k, limiter) + 8 + 12
 
 
-def bytes_per_cell_step(rk: int, elem: int) -> int:
-    """Algorithmic HBM bytes: RK2 reads U^n, writes U1, reads U1 and U^n, writes U^{n+1} (5 passes of 4 comps)."""
+def bytes_per_cell_step(rk: int, elem: int, nc: int = 4) -> int:
+    """Algorithmic HBM bytes: RK2 reads U^n, writes U1, reads U1 and U^n, writes U^{n+1} (5 passes of nc
+    components; RK3: 8)."""
     passes = 5 if rk == 2 else 8
-    return passes * 4 * elem
+    return passes * nc * elem
 
 
 def cpu_baseline(w, U, budget_s: float, table=None):
@@ -97,7 +104,7 @@ def cpu_baseline(w, U, budget_s: float, table=None):
         "unit": "cell-updates/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": f"first {steps} RK2 step(s) of the same {w.n[0]}x{w.n[1]}x{w.n[2]} workload, FP64 C oracle, "
+        "sample": f"first {steps} RK{w.rk} step(s) of the same {w.n[0]}x{w.n[1]}x{w.n[2]} workload, FP64 C oracle, "
                   f"OpenMP over grid lines, {t_total:.1f} s",
     }
 
@@ -105,7 +112,8 @@ def cpu_baseline(w, U, budget_s: float, table=None):
 def upload(U, tdt):
     import numpy as np
     import torch
-    return [torch.from_numpy(np.ascontiguousarray(U[c]).ravel()).to(device="cuda", dtype=tdt) for c in range(4)]
+    return [torch.from_numpy(np.ascontiguousarray(U[c]).ravel()).to(device="cuda", dtype=tdt)
+            for c in range(U.shape[0])]
 
 
 def run_single(args, w, U, table=None, jet_x0=None):
@@ -116,7 +124,9 @@ def run_single(args, w, U, table=None, jet_x0=None):
     dev = upload(U, tdt)
     flags = mf.MF_FLAG_UNSPLIT_HANCOCK if args.unsplit_hancock else 0
     g = mf.Grid([mf.desc_from_workload(w, mf.MF_F64 if args.dtype == "f64" else mf.MF_F32, flags)], [dev])
-    if table is None:
+    if "gamma" in w.extra:
+        g.set_eos_gamma(w.extra["gamma"])
+    elif table is None:
         g.set_eos_ideal(w.cs2)
     else:
         g.set_eos_table(*table)
@@ -305,10 +315,12 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's own count)")
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["hotspot", "shock", "jet", "ensemble", "crossover", "seed"],
+    ap.add_argument("--workload", choices=["hotspot", "shock", "jet", "ensemble", "crossover", "seed", "sod"],
                     default="hotspot",
-                    help="seed: the learned seed's kernels alone (network forward, gradient, Adam, seeded con2prim)")
-    ap.add_argument("--n", type=int, default=None, help="cells per axis (hotspot / jet)")
+                    help="seed: the learned seed's kernels alone (network forward, gradient, Adam, seeded con2prim); "
+                         "sod: the Sod tube of the ideal gas with the conserved charge, 500 cells along x, "
+                         "extended to n x n cells across (periodic)")
+    ap.add_argument("--n", type=int, default=None, help="cells per axis (hotspot / jet), across the tube (sod)")
     ap.add_argument("--events", type=int, default=None, help="events (ensemble / crossover)")
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--eos", choices=["ideal", "table"], default="ideal",
@@ -367,6 +379,15 @@ def main(argv=None):
         jet_x0 = I.jet_start(w)
         desc = (f"jet {w.n[0]}^3 hot spots (seed {w.seed}) + point jet v=0.999 dE/dx=5 sigma=0.3, superbee, "
                 f"k={w.k}, RK{w.rk}, dt={w.dt:g}")
+    elif args.workload == "sod":
+        if args.dtype != "f64":
+            print("bench.py: the charge runs in FP64 only", file=sys.stderr)
+            return 2
+        nt = args.n or 96
+        w = I.sod_workload(ny=nt, nz=nt)
+        desc = (f"Sod tube {w.n[0]}x{w.n[1]}x{w.n[2]} (500 cells of 0.02 along x, n=10|1, p=13.33|0 at rest, "
+                f"periodic across), ideal gas gamma=5/3 with the conserved charge, minmod, k={w.k}, RK{w.rk}, "
+                f"dt={w.dt:g}")
     else:
         w = I.shock_workload()
         desc = "shock tube 200x16x16, e=10|1, minmod, k=2, RK2, dt=0.03"
@@ -381,7 +402,13 @@ def main(argv=None):
     value = w.cells * args.steps / (ms_total / 1e3)
     n_launch = sum(klaunch)
     avg_launch_ms = sum(kms) / max(n_launch, 1)
-    if table is None:
+    newton_flops = None
+    if "gamma" in w.extra:
+        # Newton iterations per sweep launch: those of the step after the timed ones, over its sweeps
+        fl_axis = flops_per_cell_axis(w.k, w.limiter, C2P_FLUX_GAS, nc=5)
+        fl_launch = fl_axis * w.cells + NEWTON_ITER_FLOPS_GAS * st["newton_iters"] / (3 * w.rk)
+        newton_flops = NEWTON_ITER_FLOPS_GAS
+    elif table is None:
         fl_axis = flops_per_cell_axis(w.k, w.limiter)
         if args.unsplit_hancock:
             # the sweeps add the pre-pass's correction to both faces (8) instead of the per-axis
@@ -392,8 +419,9 @@ def main(argv=None):
         # Newton iterations per sweep launch: those of the step after the timed ones, over its 6 sweeps
         fl_axis = flops_per_cell_axis(w.k, w.limiter, C2P_FLUX_TABLE)
         fl_launch = fl_axis * w.cells + NEWTON_ITER_FLOPS * st["newton_iters"] / (3 * w.rk)
+        newton_flops = NEWTON_ITER_FLOPS
     achieved_tflops = fl_launch / (avg_launch_ms / 1e3) / 1e12
-    hbm_bytes = bytes_per_cell_step(w.rk, elem)
+    hbm_bytes = bytes_per_cell_step(w.rk, elem, 5 if w.extra.get("charge") else 4)
     hbm_gbs = value * hbm_bytes / 1e9
     out = {
         "metric": METRIC,
@@ -439,6 +467,11 @@ def main(argv=None):
         out["roofline"]["note"] = (f"tabulated EoS: {C2P_FLUX_TABLE} flops per con2prim + flux (bracket, one "
                                    f"piece lookup of p and dp/de, velocity, fluxes) and {NEWTON_ITER_FLOPS} per "
                                    "Newton iteration, iterations measured on the step after the timed ones")
+    elif newton_flops is not None:
+        out["roofline"]["newton_iters_per_step"] = st["newton_iters"]
+        out["roofline"]["note"] = (f"ideal gas with the charge (5 components): {C2P_FLUX_GAS} flops per con2prim + "
+                                   f"flux (the residual at p = 0, velocity, fluxes) and {NEWTON_ITER_FLOPS_GAS} per "
+                                   "Newton iteration on f(p), iterations measured on the step after the timed ones")
     if args.cpu_budget > 0 and args.workload != "jet":
         out["cpu_baseline"] = cpu_baseline(w, U, args.cpu_budget, table)
     if (args.compare_steps > 0 and args.workload == "hotspot" and table is None and args.dtype == "f64"

@@ -290,13 +290,26 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ P, c
 }
 
 // grad[p] = sum over wavefronts of part[w][p] (fixed order); loss = sum sq / B.
+// The partials are loaded kBatch at a time before they are added (in order),
+// so their latencies overlap: a training batch has few wavefronts of partials
+// per thread, and one load in flight at a time left the kernel latency-bound.
 __global__ void k_mlp_reduce(const float* __restrict__ part, int nwaves, int64_t B, float* __restrict__ grad,
                              float* __restrict__ loss)
 {
+    constexpr int kBatch = 16;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p > kMlpParams) return;
+    const float* col = part + p;
     float acc = 0.0f;
-    for (int w = 0; w < nwaves; w++) acc += part[(int64_t)w * (kMlpParams + 1) + p];
+    int w = 0;
+    for (; w + kBatch <= nwaves; w += kBatch) {
+        float x[kBatch];
+#pragma unroll
+        for (int i = 0; i < kBatch; i++) x[i] = col[(int64_t)(w + i) * (kMlpParams + 1)];
+#pragma unroll
+        for (int i = 0; i < kBatch; i++) acc += x[i];
+    }
+    for (; w < nwaves; w++) acc += col[(int64_t)w * (kMlpParams + 1)];
     if (p < kMlpParams) grad[p] = acc;
     else if (loss) *loss = acc / (float)B;
 }

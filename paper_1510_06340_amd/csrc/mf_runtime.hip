@@ -172,13 +172,13 @@ AxisGeom axis_geom(const int32_t n[3], int d)
 
 // x sweep (lanes along x): chunks of 64 row items per wavefront, chosen to
 // give about two full rounds of the kernel's resident wavefronts on every
-// SIMD (waves_per_simd, from its occupancy).  With the table EoS the cost per
-// cell varies with the local Newton iterations, and smaller work units (about
-// four rounds) balance it better.
-int auto_chunks_x(const AxisGeom& g, bool table, int waves_per_simd)
+// SIMD (waves_per_simd, from its occupancy).  Where con2prim runs a Newton
+// solve (the table EoS, the ideal gas) the cost per cell varies with the local
+// iterations, and smaller work units (about four rounds) balance it better.
+int auto_chunks_x(const AxisGeom& g, bool newton, int waves_per_simd)
 {
     const int64_t items = g.nlines * ((int64_t)g.N + 2);
-    const int64_t target_waves = 256LL * 4 * waves_per_simd * (table ? 4 : 2);
+    const int64_t target_waves = 256LL * 4 * waves_per_simd * (newton ? 4 : 2);
     int64_t cpw = (items + 64 * target_waves - 1) / (64 * target_waves);
     return (int)std::max<int64_t>(1, std::min<int64_t>(cpw, 64));
 }
@@ -187,12 +187,13 @@ int auto_chunks_x(const AxisGeom& g, bool table, int waves_per_simd)
 // of the kernel's resident wavefronts (waves_per_simd, from its occupancy) on
 // every SIMD of the 256 compute units (the second round balances the tail),
 // but at least 16 cells per segment (each segment recomputes two
-// reconstructions and one interface).  With the table EoS (uneven cost per
-// cell): 16 wavefronts per SIMD (five rounds of three) and at least 8 cells.
-int auto_seg(const AxisGeom& g, bool table, int waves_per_simd)
+// reconstructions and one interface).  Where con2prim runs a Newton solve
+// (uneven, latency-bound cost per cell): 16 wavefronts per SIMD (five rounds
+// of three) and at least 8 cells.
+int auto_seg(const AxisGeom& g, bool newton, int waves_per_simd)
 {
-    const int64_t target_threads = 256LL * 4 * 64 * (table ? 16 : 2 * waves_per_simd);
-    int64_t min_cells = table ? 8 : 16;
+    const int64_t target_threads = 256LL * 4 * 64 * (newton ? 16 : 2 * waves_per_simd);
+    int64_t min_cells = newton ? 8 : 16;
     // Small grids (under one wavefront per compute unit at that length) take
     // segments down to 4 cells: the march's latency, not the overlap, bounds them.
     if (g.nlines * ((g.N + min_cells - 1) / min_cells) < 256LL * 64) min_cells = 4;
@@ -280,19 +281,21 @@ int64_t axis_tiles(const Event& ev, int d, int seg, int block)
     return ((geo.nlines + block - 1) / block) * nseg;
 }
 
-int default_shape(const Event& ev, int d, bool table, int waves_per_simd)
+int default_shape(const Event& ev, int d, bool newton, int waves_per_simd)
 {
     const AxisGeom geo = axis_geom(ev.d.n, d);
-    return d == 0 ? auto_chunks_x(geo, table, waves_per_simd) : auto_seg(geo, table, waves_per_simd);
+    return d == 0 ? auto_chunks_x(geo, newton, waves_per_simd) : auto_seg(geo, newton, waves_per_simd);
 }
 
 // What a stage needs besides the event: the stream, launch-shape overrides
-// (0 = automatic), the block size, whether the EoS is tabulated, and the
-// handle that collects kernel timings (nullptr: no timing).
+// (0 = automatic), the block size, whether con2prim runs a Newton solve (the
+// table EoS and the ideal gas: finer work units) and whether the EoS is
+// tabulated, and the handle that collects kernel timings (nullptr: no timing).
 struct StageCtx {
     hipStream_t stream;
     int seg_override[3];
     int block;
+    bool newton;
     bool table;
     mf_grid_s* prof;
 };
@@ -303,6 +306,7 @@ StageCtx stage_ctx(mf_grid_s* g)
     c.stream = g->stream;
     for (int q = 0; q < 3; q++) c.seg_override[q] = g->seg_override[q];
     c.block = g->block;
+    c.newton = g->eos_kind == MF_EOS_TABLE || g->eos_kind == MF_EOS_GAMMA;
     c.table = g->eos_kind == MF_EOS_TABLE;
     c.prof = g->profiling ? g : nullptr;
     return c;
@@ -351,7 +355,9 @@ int run_stage(const StageCtx& cx, const Eos& eos, Event& ev, unsigned long long*
                 if (ev.nc == 4) waves = sweep_waves_per_simd<T, Eos>(d, ev.d.limiter, ev.jet && d == 2, cx.block);
             }
         }
-        int seg = cx.seg_override[d] > 0 ? cx.seg_override[d] : default_shape(ev, d, cx.table, waves);
+        // the ideal gas's x sweep (four wavefronts per SIMD) ran 5% slower with the finer chunks
+        const bool fine = cx.newton && (d > 0 || cx.table);
+        int seg = cx.seg_override[d] > 0 ? cx.seg_override[d] : default_shape(ev, d, fine, waves);
         if (d > 0) seg = std::min(seg, geo.N);
         SweepArgs<T> a = make_sweep_args<T>(ev, d, seg, stats, uin, u0, out, kind, dt, want_smax);
         const bool jet = ev.jet && d == 2;
