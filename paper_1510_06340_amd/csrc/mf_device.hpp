@@ -263,11 +263,16 @@ template <typename T> struct EosIdeal {
 // e_i with node slopes m_i (Fritsch-Carlson), p = p_0 e / e_0 below the first
 // node and linear with the end slope above the last.
 //
-// The table holds n + 1 pieces of 64 bytes, (lo, hi, x, w) and
-// (y, c1, c2, c3), with p(e) = y + t (c1 + t (c2 + t c3)), t = (e - x) w on
-// [lo, hi): piece 0 is the extrapolation below e_0, pieces 1 .. n-1 the
-// cubics between nodes (the Hermite cubic in powers of t), piece n the
-// extrapolation above e_{n-1}.  One piece is one lookup: two 32-byte loads.
+// The table holds n + 1 pieces of 48 bytes, (x, w), (y, c1), (c2, c3), with
+// p(e) = y + t (c1 + t (c2 + t c3)), t = (e - x) w on [x, x + 1/w), i.e.
+// 0 <= t < 1: piece 0 is the extrapolation below e_0 (x = 0, w = 1/e_0),
+// pieces 1 .. n-1 the cubics between nodes (the Hermite cubic in powers of
+// t), piece n the extrapolation above e_{n-1} (w = 2^-60, so t < 1 up to
+// e ~ 1e18).  One piece is one lookup: three 16-byte loads.  A first-guess
+// piece is accepted where 0 <= t < 1; elsewhere the piece is found by
+// comparing e with the pieces' origins (exact), so either way e lies in the
+// piece up to the rounding of t at its upper end, where the two cubics
+// meeting at the node agree to rounding (the interpolant is C^1).
 //
 // con2prim (Sec. 2.6): the fixed point v = |M| / (E + p(E - |M| v)) is the
 // root of g(e) = e - E + |M|^2 / (E + p(e)) on the bracket [E (1 - m^2), E],
@@ -281,7 +286,7 @@ template <typename T> struct EosIdeal {
 struct EosTable {
     static constexpr int kWaves = 2;  // minimum waves per SIMD the sweeps are compiled for (they get 3-4)
     static constexpr bool kLoadLAhead = true;  // the y sweep loads L ahead (latency-bound at 3 waves)
-    const double4* rec;  // 2 (n + 1) records: piece k = rec[2k], rec[2k + 1]
+    const double2* rec;  // 3 (n + 1) records: piece k = rec[3k] (x, w), rec[3k + 1] (y, c1), rec[3k + 2] (c2, c3)
     int32_t n;           // nodes
     int32_t log_uniform; // piece from log2(e) (then a fix-up); else bisection
     float lg0;           // log2 e_0 - (log2 e_{n-1} - log2 e_0) / (n - 1): piece k covers [k, k + 1) in
@@ -307,19 +312,26 @@ struct EosTable {
     // only defined to that absolute level), and the iterate is accepted.
     static constexpr double kNewtonAbsTol = 1e-15;
 
-    // Piece k: records 2k and 2k + 1 (the table is far below 4 GiB, so a 32-bit byte offset).
-    __device__ __forceinline__ const double4* piece_ptr(int k) const
+    // Piece k: records 3k .. 3k + 2 (the table is far below 4 GiB, so a 32-bit byte offset).
+    __device__ __forceinline__ const double2* piece_ptr(int k) const
     {
-        return reinterpret_cast<const double4*>(reinterpret_cast<const char*>(rec) + (uint32_t)k * 64u);
+        return reinterpret_cast<const double2*>(reinterpret_cast<const char*>(rec) + (uint32_t)k * 48u);
     }
 
-    // Cubic of one piece at e: p and dp/de.
-    __device__ __forceinline__ static void cubic(double e, const double4& a, const double4& b, double& p,
-                                                 double& dp)
+    // Cubic of one piece at e: p and dp/de; returns t (the piece holds e for 0 <= t < 1).
+    __device__ __forceinline__ static double cubic(double e, const double2& a, const double2& b, const double2& c,
+                                                   double& p, double& dp)
     {
-        const double t = (e - a.z) * a.w;
-        p = fma(t, fma(t, fma(t, b.w, b.z), b.y), b.x);
-        dp = a.w * fma(t, fma(t, 3.0 * b.w, 2.0 * b.z), b.y);
+        const double t = (e - a.x) * a.y;
+        p = fma(t, fma(t, fma(t, c.y, c.x), b.y), b.x);
+        dp = a.y * fma(t, fma(t, 3.0 * c.y, 2.0 * c.x), b.y);
+        return t;
+    }
+
+    // Lanes whose first-guess piece does not hold their argument (t outside [0, 1), or NaN).
+    __device__ __forceinline__ static uint64_t outside(double t)
+    {
+        return lanes_where(!(t >= 0.0)) | lanes_where(!(t < 1.0));
     }
 
     // p(e) and dp/de (e >= 0).  On log-uniform nodes the piece comes from a
@@ -334,34 +346,35 @@ struct EosTable {
         return (int)u;                                                 // in [0, n]
     }
 
-    // The piece of e found by stepping from piece k, and its cubic.
+    // The piece of e found by stepping from piece k (piece j starts at the origin
+    // of its record and ends at the next piece's), and its cubic.
     __device__ __forceinline__ void walk(double e, int k, double& p, double& dp) const
     {
         while (k > 0 && e < piece_ptr(k)[0].x) k--;
-        while (k < n && e >= piece_ptr(k)[0].y) k++;
-        cubic(e, piece_ptr(k)[0], piece_ptr(k)[1], p, dp);
+        while (k < n && e >= piece_ptr(k + 1)[0].x) k++;
+        const double2* r = piece_ptr(k);
+        cubic(e, r[0], r[1], r[2], p, dp);
     }
 
     __device__ __forceinline__ void eval(double e, double& p, double& dp) const
     {
         if (log_uniform) {
             const int k = guess_piece(e);
-            const double4* r = piece_ptr(k);
-            const double4 a = r[0];
-            const double4 b = r[1];
-            cubic(e, a, b, p, dp);
-            const uint64_t off = lanes_where(e < a.x) | lanes_where(e >= a.y);
+            const double2* r = piece_ptr(k);
+            const double2 a = r[0], b = r[1], c = r[2];
+            const uint64_t off = outside(cubic(e, a, b, c, p, dp));
             if (off != 0) {
                 if (lane_in(off)) walk(e, k, p, dp);
             }
         } else {
-            int lo = 0, hi = n + 1;  // rec[2 lo].x <= e < rec[2 hi].x
+            int lo = 0, hi = n + 1;  // origin of piece lo <= e < origin of piece hi
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
-                if (rec[2 * mid].x <= e) lo = mid;
+                if (piece_ptr(mid)[0].x <= e) lo = mid;
                 else hi = mid;
             }
-            cubic(e, piece_ptr(lo)[0], piece_ptr(lo)[1], p, dp);
+            const double2* r = piece_ptr(lo);
+            cubic(e, r[0], r[1], r[2], p, dp);
         }
     }
 
@@ -372,12 +385,12 @@ struct EosTable {
     {
         if (log_uniform) {
             const int kA = guess_piece(eA), kB = guess_piece(eB);
-            const double4 aA = piece_ptr(kA)[0], bA = piece_ptr(kA)[1];
-            const double4 aB = piece_ptr(kB)[0], bB = piece_ptr(kB)[1];
-            cubic(eA, aA, bA, pA, dpA);
-            cubic(eB, aB, bB, pB, dpB);
-            const uint64_t offA = lanes_where(eA < aA.x) | lanes_where(eA >= aA.y);
-            const uint64_t offB = lanes_where(eB < aB.x) | lanes_where(eB >= aB.y);
+            const double2* rA = piece_ptr(kA);
+            const double2* rB = piece_ptr(kB);
+            const double2 aA = rA[0], bA = rA[1], cA = rA[2];
+            const double2 aB = rB[0], bB = rB[1], cB = rB[2];
+            const uint64_t offA = outside(cubic(eA, aA, bA, cA, pA, dpA));
+            const uint64_t offB = outside(cubic(eB, aB, bB, cB, pB, dpB));
             if ((offA | offB) != 0) {
                 if (lane_in(offA)) walk(eA, kA, pA, dpA);
                 if (lane_in(offB)) walk(eB, kB, pB, dpB);

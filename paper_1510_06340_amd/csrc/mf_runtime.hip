@@ -941,25 +941,26 @@ int mf_set_eos(mf_grid_t g, int32_t kind, double cs2, const double* e_tab, const
         return fail(MF_ERR_ARG, "the seed network must be 2-64-64-1 with all weights and output 0 or 1");
     std::vector<double> m;
     monotone_slopes(n_tab, e_tab, p_tab, m);
-    // n + 1 pieces (lo, hi, x, w, y, c1, c2, c3): p = y + t (c1 + t (c2 + t c3)), t = (e - x) w on [lo, hi).
-    // Piece 0: p_0 e / e_0 below e_0; pieces 1 .. n-1: the Hermite cubic of
-    // [e_{i-1}, e_i] with end values p and slopes m, in powers of t; piece n:
-    // linear with the end slope above e_{n-1}.
-    std::vector<double> rec(8 * ((size_t)n_tab + 1));
-    auto put = [&](int k, double lo, double hi, double x, double w, double y, double c1, double c2, double c3) {
-        double* r = &rec[8 * (size_t)k];
-        r[0] = lo; r[1] = hi; r[2] = x; r[3] = w; r[4] = y; r[5] = c1; r[6] = c2; r[7] = c3;
+    // n + 1 pieces (x, w, y, c1, c2, c3): p = y + t (c1 + t (c2 + t c3)), t = (e - x) w, the
+    // piece holding e where 0 <= t < 1.  Piece 0: p_0 e / e_0 below e_0 (x = 0, w = 1 / e_0);
+    // pieces 1 .. n-1: the Hermite cubic of [e_{i-1}, e_i] with end values p and slopes m, in
+    // powers of t; piece n: linear with the end slope above e_{n-1}, with w = 2^-60 so that
+    // t < 1 far beyond any state (the scaling by a power of two is exact).
+    std::vector<double> rec(6 * ((size_t)n_tab + 1));
+    auto put = [&](int k, double x, double w, double y, double c1, double c2, double c3) {
+        double* r = &rec[6 * (size_t)k];
+        r[0] = x; r[1] = w; r[2] = y; r[3] = c1; r[4] = c2; r[5] = c3;
     };
-    put(0, 0.0, e_tab[0], 0.0, 1.0, 0.0, p_tab[0] / e_tab[0], 0.0, 0.0);
+    put(0, 0.0, 1.0 / e_tab[0], 0.0, p_tab[0], 0.0, 0.0);
     for (int i = 1; i < n_tab; i++) {
         const double h = e_tab[i] - e_tab[i - 1];
         const double y0 = p_tab[i - 1], y1 = p_tab[i];
         const double c1 = h * m[i - 1];
         const double c2 = 3.0 * (y1 - y0) - h * (2.0 * m[i - 1] + m[i]);
         const double c3 = 2.0 * (y0 - y1) + h * (m[i - 1] + m[i]);
-        put(i, e_tab[i - 1], e_tab[i], e_tab[i - 1], 1.0 / h, y0, c1, c2, c3);
+        put(i, e_tab[i - 1], 1.0 / h, y0, c1, c2, c3);
     }
-    put(n_tab, e_tab[n_tab - 1], HUGE_VAL, e_tab[n_tab - 1], 1.0, p_tab[n_tab - 1], m[n_tab - 1], 0.0, 0.0);
+    put(n_tab, e_tab[n_tab - 1], 0x1p-60, p_tab[n_tab - 1], m[n_tab - 1] * 0x1p60, 0.0, 0.0);
     // log-uniform nodes: the interval comes from log2(e) and a +-1 fix-up
     const double l0 = std::log2(e_tab[0]), l1 = std::log2(e_tab[n_tab - 1]);
     const double dl = (l1 - l0) / (n_tab - 1);
@@ -978,7 +979,7 @@ int mf_set_eos(mf_grid_t g, int32_t kind, double cs2, const double* e_tab, const
     if (rc) return rc;
     MF_HIP(hipMemcpy(g->table_dev, rec.data(), rec.size() * sizeof(double), hipMemcpyHostToDevice));
     EosTable& t = g->table;
-    t.rec = (const double4*)g->table_dev;
+    t.rec = (const double2*)g->table_dev;
     t.n = n_tab;
     t.log_uniform = log_uniform ? 1 : 0;
     t.lg0 = (float)(l0 - dl);  // piece k + 1 starts at node k

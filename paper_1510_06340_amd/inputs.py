@@ -24,6 +24,10 @@ that are not available; seeded Gaussian hot spots stand in for them):
 * ``ensemble``  64 events with per-axis sizes drawn from {96, 112, ..., 192},
                 dx = 0.1, hot spots, MC, k = 3, dt = 0.03, 100 steps.
 * ``crossover`` 32 events of 192^3 under the tabulated crossover EoS.
+* ``sod``       the paper's Sod tube of the ideal gas with the conserved
+                charge: 500 cells of 0.02 along x, RK3, k = 4, 800 steps.
+* ``ellipsoidal`` the paper's ellipsoidal flow of pressureless dust with the
+                charge: 120^3 cells of 0.1 from t = 2, RK3, k = 4, 50 steps.
 """
 from __future__ import annotations
 
