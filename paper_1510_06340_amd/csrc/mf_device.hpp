@@ -284,7 +284,7 @@ template <typename T> struct EosIdeal {
 // is replaced by bisection.  FP64 only.
 // ---------------------------------------------------------------------------
 struct EosTable {
-    static constexpr int kWaves = 2;  // minimum waves per SIMD the sweeps are compiled for (they get 3-4)
+    static constexpr int kWaves = 3;  // minimum waves per SIMD the sweeps are compiled for
     static constexpr bool kLoadLAhead = true;  // the y sweep loads L ahead (latency-bound at 3 waves)
     const double2* rec;  // 3 (n + 1) records: piece k = rec[3k] (x, w), rec[3k + 1] (y, c1), rec[3k + 2] (c2, c3)
     int32_t n;           // nodes
@@ -311,6 +311,14 @@ struct EosTable {
     // below kNewtonAbsTol E is rounding noise (for |M| -> E the root e << E is
     // only defined to that absolute level), and the iterate is accepted.
     static constexpr double kNewtonAbsTol = 1e-15;
+    // The last first-guess piece this thread loaded (the thread's copy of the
+    // EoS lives in registers).  Neighbouring cells of smooth flow look up the
+    // same piece again and again; a wavefront whose lanes all guess the cached
+    // piece takes it from registers and issues no loads.  The cache is keyed
+    // by the first guess, so every lane evaluates the piece it would have
+    // loaded: results do not depend on the cache's history.
+    mutable int32_t ck = -1;
+    mutable double2 ca, cb, cc;
 
     // Piece k: records 3k .. 3k + 2 (the table is far below 4 GiB, so a 32-bit byte offset).
     __device__ __forceinline__ const double2* piece_ptr(int k) const
@@ -360,9 +368,14 @@ struct EosTable {
     {
         if (log_uniform) {
             const int k = guess_piece(e);
-            const double2* r = piece_ptr(k);
-            const double2 a = r[0], b = r[1], c = r[2];
-            const uint64_t off = outside(cubic(e, a, b, c, p, dp));
+            if (lanes_where(k != ck) != 0) {   // some lane needs another piece
+                const double2* r = piece_ptr(k);
+                ca = r[0];
+                cb = r[1];
+                cc = r[2];
+                ck = k;
+            }
+            const uint64_t off = outside(cubic(e, ca, cb, cc, p, dp));
             if (off != 0) {
                 if (lane_in(off)) walk(e, k, p, dp);
             }
@@ -385,12 +398,22 @@ struct EosTable {
     {
         if (log_uniform) {
             const int kA = guess_piece(eA), kB = guess_piece(eB);
-            const double2* rA = piece_ptr(kA);
-            const double2* rB = piece_ptr(kB);
-            const double2 aA = rA[0], bA = rA[1], cA = rA[2];
-            const double2 aB = rB[0], bB = rB[1], cB = rB[2];
-            const uint64_t offA = outside(cubic(eA, aA, bA, cA, pA, dpA));
-            const uint64_t offB = outside(cubic(eB, aB, bB, cB, pB, dpB));
+            uint64_t offA, offB;
+            if ((lanes_where(kA != ck) | lanes_where(kB != ck)) != 0) {   // some lane needs another piece
+                const double2* rA = piece_ptr(kA);
+                const double2* rB = piece_ptr(kB);
+                const double2 aA = rA[0], bA = rA[1], cA = rA[2];
+                const double2 aB = rB[0], bB = rB[1], cB = rB[2];
+                offA = outside(cubic(eA, aA, bA, cA, pA, dpA));
+                offB = outside(cubic(eB, aB, bB, cB, pB, dpB));
+                ca = aB;
+                cb = bB;
+                cc = cB;
+                ck = kB;
+            } else {
+                offA = outside(cubic(eA, ca, cb, cc, pA, dpA));
+                offB = outside(cubic(eB, ca, cb, cc, pB, dpB));
+            }
             if ((offA | offB) != 0) {
                 if (lane_in(offA)) walk(eA, kA, pA, dpA);
                 if (lane_in(offB)) walk(eB, kB, pB, dpB);

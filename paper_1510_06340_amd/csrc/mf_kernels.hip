@@ -298,11 +298,12 @@ __device__ __forceinline__ void sweep_line(const SweepArgs<T>& a, const Eos& eos
 }
 
 // Waves per SIMD the register budget is sized for.  The jet source adds a
-// few live values to the z sweep, which at 4 waves would spill.
+// few live values to the z sweep, which at 4 waves (3 with the table EoS)
+// would spill: it gets one wavefront fewer.
 template <class Eos, bool JET>
 constexpr int sweep_waves()
 {
-    return JET && Eos::kWaves > 3 ? 3 : Eos::kWaves;
+    return JET && Eos::kWaves > 2 ? Eos::kWaves - 1 : Eos::kWaves;
 }
 
 template <typename T, int D, int LIM, class Eos, bool JET, bool UNSPLIT = false, int NC = 4>
