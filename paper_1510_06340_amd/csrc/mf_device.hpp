@@ -299,7 +299,7 @@ struct EosTable {
     // registers in the sweeps)
     const float* seed;   // [kSeedG0][kSeedG1] or nullptr (plain solve)
     int32_t seed_output;             // 0: grid holds ln e; 1: the bracket fraction (E - e) E / |M|^2
-    static constexpr double kSeedMinM2 = 1e-3;  // ln e seed only where (|M|/E)^2 > this
+    static constexpr double kSeedMinM2 = 2e-2;  // ln e seed only where (|M|/E)^2 > this
     // Newton stops when |de| <= kNewtonTol e and returns e - de.  The error of
     // that iterate is bounded by (max |g''| / (2 min g')) de^2 with
     // g' >= 1 - m^2 max p' and |g''| <= m^2 (2 max p'^2 / E + max |p''|): for
@@ -520,11 +520,13 @@ struct EosTable {
             const double q = M2 * Math<double>::rcp(E);
             lo = E - q;
             e_start = 0.5 * (lo + E);
-            // A guess of ln e carries an error of about 1e-3 relative, which beats the
-            // bracket midpoint (off by about m^2 E / 4) only where m^2 > kSeedMinM2, so
-            // that seed is consulted only there (wavefronts without such a state skip
-            // the lookup).  A guess of the bracket fraction is scaled by the bracket and
-            // consulted wherever |M| > 0.
+            // A guess of ln e carries an error of about 1e-4 to 1e-2 relative; the
+            // bracket midpoint is off by about m^2 E / 4.  The guess saves a Newton
+            // step only where m^2 > kSeedMinM2 (on the crossover workload a threshold
+            // of 1e-3 saved no more iterations than 2e-2), so that seed is consulted
+            // only there (wavefronts without such a state skip the lookup).  A guess
+            // of the bracket fraction is scaled by the bracket and consulted wherever
+            // |M| > 0.
             if (seed) {
                 const bool wide = q > (seed_output == 1 ? 0.0 : kSeedMinM2 * E);
                 if (__any(wide)) {
