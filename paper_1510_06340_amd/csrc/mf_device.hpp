@@ -44,6 +44,20 @@ template <> struct Math<double> {
         double d = __builtin_fma(-g, g, x);
         return __builtin_fma(d, h, g);
     }
+    // sqrt(x) as sqrt() gives it, and 1/sqrt(x) from the same Goldschmidt step
+    // (2h, relative error about 1e-15: for derivatives, not for results).
+    static __device__ __forceinline__ double sqrt_rsq(double x, double& rs)
+    {
+        double y = __builtin_amdgcn_rsq(x);
+        double g = x * y;
+        double h = 0.5 * y;
+        double r = __builtin_fma(-g, h, 0.5);
+        g = __builtin_fma(g, r, g);
+        h = __builtin_fma(h, r, h);
+        double d = __builtin_fma(-g, g, x);
+        rs = 2.0 * h;
+        return __builtin_fma(d, h, g);
+    }
     // sqrt that also returns 0 for x == 0 (rsq(0) is +inf).
     static __device__ __forceinline__ double sqrt0(double x) { return x > 0.0 ? sqrt(x) : 0.0; }
     // sqrt for any x >= 0: below 2^-767 (where the hardware estimate does not hold, e.g. the
@@ -708,16 +722,19 @@ struct EosGamma {
         return g;
     }
 
-    // f(p) and f'(p); iw = 1 / (E + p) out.
+    // f(p) and f'(p); iw = 1 / (E + p) out.  f' takes W = 1/sqrt(1 - v^2) from
+    // the square root's own step (about 1e-15 relative), which the Newton step
+    // tolerates: only f decides the root.
     __device__ __forceinline__ void residual(double E, double M2, double R, double p, double& f, double& fp,
                                              double& iw) const
     {
         iw = Math<double>::rcp(E + p);
         const double v2 = M2 * iw * iw;
-        const double sq = Math<double>::sqrt(1.0 - v2);   // 1 / W
+        double W;
+        const double sq = Math<double>::sqrt_rsq(1.0 - v2, W);   // 1 / W, and W
         const double e = E - M2 * iw;
         f = gm1 * (e - R * sq) - p;
-        fp = gm1 * v2 * (1.0 - R * iw * Math<double>::rcp(sq)) - 1.0;
+        fp = gm1 * v2 * (1.0 - R * iw * W) - 1.0;
     }
 
     // Pressure of a live state (E > 0, |M| < E, R >= 0).
@@ -731,7 +748,9 @@ struct EosGamma {
         double p = fmin(f, hi);
         for (int it = 1;; it++) {
             residual(E, M2, R, p, f, fp, iw);
-            const double dp = f * Math<double>::rcp(fp);   // fp < 0
+            // fp < 0 (about -1).  The hardware reciprocal (5e-8 relative) suffices: a
+            // step accepted at |dp| <= kTol (E + p) then errs by below 1e-17 (E + p).
+            const double dp = f * __builtin_amdgcn_rcp(fp);
             double pn = p - dp;
             cnt.iters += cnt.w;
             if (fabs(dp) <= kTol * (E + p)) return fmax(pn, 0.0);
