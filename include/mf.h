@@ -220,9 +220,10 @@ int mf_mlp_grad(const float* params, const float* X, const float* t, int64_t n, 
                 float* work, int64_t work_floats, void* stream);
 /* For callers that cannot allocate device memory (code under HIP graph capture,
  * tight training or serving loops, harnesses that forbid allocation): the same
- * gradient as mf_mlp_grad, with its per-wavefront partial gradients kept in a
- * library-owned static device array instead of a caller workspace.  The array
- * holds the partials of up to MF_MLP_NOALLOC_MAX_N samples (4.5 MB); each GPU
+ * gradient as mf_mlp_grad, with its partial gradients (one per block of 64
+ * samples) kept in a library-owned static device array instead of a caller
+ * workspace.  The array holds the partials of up to MF_MLP_NOALLOC_MAX_N
+ * samples (1.1 MB); each GPU
  * the library runs on holds its own copy until the process ends.  n must lie
  * in [1, MF_MLP_NOALLOC_MAX_N] (else MF_ERR_ARG).  The call runs on the current
  * device, and stream must belong to it.  It allocates nothing: no hipMalloc,

@@ -9,8 +9,13 @@
 // agree between A and B, so a product over samples may take its K slots in
 // any order (the weight gradient uses that to feed the accumulator layout of
 // the forward pass straight back in as its A operand).
-// One wavefront owns 64 samples (4 M-tiles); layers 1 and 3 (K = 2, N = 1)
-// run on the vector ALUs.
+// Inference: one wavefront owns 64 samples (4 M-tiles).  Training: one
+// wavefront owns 16 samples (1 M-tile), four to a block, so that a training
+// batch spreads over four times as many compute units; the weight gradient,
+// a product over the 16 samples, takes gfx950's K = 16 form
+// (v_mfma_f32_16x16x16_bf16: lane l holds A[l % 16][4 (l / 16) + i] and
+// B[4 (l / 16) + i][l % 16], i = 0..3).  Layers 1 and 3 (K = 2, N = 1) run
+// on the vector ALUs.
 //
 // Rounding points (the CPU reference applies the same ones):
 //   z1 = bf(W1) x + b1, h1 = tanh z1, h1b = bf(h1)
@@ -66,6 +71,11 @@ __device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c)
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+__device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
 // Shared-memory image of the weights used by the matrix-core layer (16-byte
 // aligned rows: the matrix operands are read 8 values at a time).
 struct __align__(16) MlpShared {
@@ -95,25 +105,31 @@ __device__ void load_shared(const float* __restrict__ P, MlpShared& s)
     if (threadIdx.x == 0) s.b3 = P[OFF_B3];
 }
 
-// Forward pass of one wavefront (64 samples, lane l owns sample l).
-// sA: this wavefront's [64][LDA] bf16 buffer.  Returns, in the matrix-core
-// accumulator layout, z2 (without bias) for the 4 x 4 (M, N) tiles, and y for
-// the samples 16 mt + 4 (l / 16) + i in yv[mt][i] (valid in every lane).
+// Forward pass of one wavefront over 16 MT samples.  MT = 4: lane l owns
+// sample l and computes its 64 hidden units; MT = 1: lane l computes hidden
+// units 16 (l / 16) .. 16 (l / 16) + 15 of sample l % 16 (x0, x1: that
+// sample's inputs).  sA: this wavefront's [16 MT][LDA] bf16 buffer.  Returns,
+// in the matrix-core accumulator layout, z2 (without bias) for the MT x 4
+// (M, N) tiles, and y for the samples 16 mt + 4 (l / 16) + i in yv[mt][i]
+// (valid in every lane).
+template <int MT>
 __device__ __forceinline__ void mlp_forward_wave(const MlpShared& s, unsigned short* sA, float x0, float x1,
-                                                 f32x4 acc[4][4], float yv[4][4])
+                                                 f32x4 acc[MT][4], float yv[MT][4])
 {
     const int l = threadIdx.x & 63;
-    // layer 1 (VALU): h1b of this lane's sample into row l of sA
-    for (int h = 0; h < H; h += 2) {
+    const int r = l & 15, q = l >> 4;
+    // layer 1 (VALU): h1b of the lane's sample into its row of sA
+    const int row = MT == 4 ? l : r;
+    const int h0 = MT == 4 ? 0 : 16 * q, h1 = MT == 4 ? H : 16 * q + 16;
+    for (int h = h0; h < h1; h += 2) {
         const float z0 = __builtin_fmaf(s.w1[2 * h], x0, __builtin_fmaf(s.w1[2 * h + 1], x1, 0.0f)) + s.b1[h];
         const float z1 = __builtin_fmaf(s.w1[2 * h + 2], x0, __builtin_fmaf(s.w1[2 * h + 3], x1, 0.0f)) + s.b1[h + 1];
         const unsigned int pk = (unsigned int)f2bf(tanhf(z0)) | ((unsigned int)f2bf(tanhf(z1)) << 16);
-        *(unsigned int*)&sA[l * LDA + h] = pk;
+        *(unsigned int*)&sA[row * LDA + h] = pk;
     }
     __syncthreads();
     // layer 2 (matrix cores): z2[s][n] = sum_k h1b[s][k] bf(W2)[n][k]
-    const int r = l & 15, q = l >> 4;
-    for (int mt = 0; mt < 4; mt++) {
+    for (int mt = 0; mt < MT; mt++) {
         for (int nt = 0; nt < 4; nt++) acc[mt][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
         for (int kt = 0; kt < 2; kt++) {
             const bf16x8 a = lds8(&sA[(mt * 16 + r) * LDA + kt * 32 + 8 * q]);
@@ -122,7 +138,7 @@ __device__ __forceinline__ void mlp_forward_wave(const MlpShared& s, unsigned sh
         }
     }
     // layer 3 (VALU): y[s] = sum_n bf(w3)[n] tanh(z2[s][n] + b2[n]) + b3
-    for (int mt = 0; mt < 4; mt++) {
+    for (int mt = 0; mt < MT; mt++) {
         float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         for (int nt = 0; nt < 4; nt++) {
             const int n = nt * 16 + r;
@@ -151,7 +167,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ P
     const float x1 = smp < B ? X[2 * smp + 1] : 0.0f;
     f32x4 acc[4][4];
     float yv[4][4];
-    mlp_forward_wave(s, sA[w], x0, x1, acc, yv);
+    mlp_forward_wave<4>(s, sA[w], x0, x1, acc, yv);
     const int r = l & 15, q = l >> 4;
     if (r == 0) {
         for (int mt = 0; mt < 4; mt++)
@@ -162,100 +178,93 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ P
     }
 }
 
-// Forward + backward of the mean squared error for B samples: one partial
-// gradient (kMlpParams floats, plus the partial squared-error sum) per
-// wavefront into part[wave][kMlpParams + 1].
+// Forward + backward of the mean squared error for B samples.  A block of
+// four wavefronts owns 64 samples, 16 per wavefront; each wavefront's partial
+// gradient (kMlpParams floats and its squared-error sum) goes to LDS, and the
+// block writes their sum (in a fixed order) into part[block][kMlpParams + 1].
 __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ P, const float* __restrict__ X,
                                                   const float* __restrict__ T, int64_t B, float* __restrict__ part)
 {
     __shared__ MlpShared s;
-    __shared__ __align__(16) unsigned short sA[4][64 * LDA];   // h1b per wavefront
-    __shared__ __align__(16) unsigned short sD[4][64 * LDA];   // dz2b per wavefront ([s][n])
-    __shared__ float sX[4][64][2];
+    __shared__ __align__(16) unsigned short sA[4][16 * LDA];   // h1b per wavefront ([s][k])
+    __shared__ __align__(16) unsigned short sD[4][16 * LDA];   // dz2b per wavefront ([s][n])
+    __shared__ float sX[4][16][2];
+    __shared__ float red[4][kMlpParams + 1];                   // the wavefronts' partial gradients
     load_shared(P, s);
     __syncthreads();
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int r = l & 15, q = l >> 4;
-    const int64_t base = ((int64_t)blockIdx.x * 4 + w) * 64;
-    const int64_t smp = base + l;
+    const int64_t base = ((int64_t)blockIdx.x * 4 + w) * 16;
+    const int64_t smp = base + r;   // lanes r, r + 16, r + 32, r + 48 share sample r
     const bool valid = smp < B;
     const float x0 = valid ? X[2 * smp] : 0.0f;
     const float x1 = valid ? X[2 * smp + 1] : 0.0f;
-    sX[w][l][0] = x0;
-    sX[w][l][1] = x1;
-    f32x4 acc[4][4];
-    float yv[4][4];
-    mlp_forward_wave(s, sA[w], x0, x1, acc, yv);
+    if (q == 0) {
+        sX[w][r][0] = x0;
+        sX[w][r][1] = x1;
+    }
+    f32x4 acc[1][4];
+    float yv[1][4];
+    mlp_forward_wave<1>(s, sA[w], x0, x1, acc, yv);
 
-    // dy for the samples of this lane's accumulator rows; padding samples get 0
-    float dy[4][4];
+    // dy for the samples 4 q + i of this lane's accumulator rows; padding samples get 0
+    float dy[4];
     float sq = 0.0f;
-    for (int mt = 0; mt < 4; mt++)
-        for (int i = 0; i < 4; i++) {
-            const int64_t o = base + mt * 16 + 4 * q + i;
-            const float d = o < B ? yv[mt][i] - T[o] : 0.0f;
-            dy[mt][i] = 2.0f * d / (float)B;
-            if (r == 0) sq += d * d;
-        }
+    for (int i = 0; i < 4; i++) {
+        const int64_t o = base + 4 * q + i;
+        const float d = o < B ? yv[0][i] - T[o] : 0.0f;
+        dy[i] = 2.0f * d / (float)B;
+        if (r == 0) sq += d * d;
+    }
     // dz2 = dy w3b (1 - h2^2) in the accumulator layout; dw3, db2 partials per column n
     float gw3[4] = {0, 0, 0, 0}, gb2[4] = {0, 0, 0, 0};
-    bf16x4 dzA[4][4];  // dz2b as the A operand of dW2 (rows n, columns s): same lane layout
-    for (int mt = 0; mt < 4; mt++)
-        for (int nt = 0; nt < 4; nt++) {
-            const int n = nt * 16 + r;
-            short v[4];
-            for (int i = 0; i < 4; i++) {
-                const float h2 = tanhf(acc[mt][nt][i] + s.b2[n]);
-                const float dz = dy[mt][i] * s.w3[n] * (1.0f - h2 * h2);
-                gw3[nt] = __builtin_fmaf(dy[mt][i], h2, gw3[nt]);
-                gb2[nt] += dz;
-                const unsigned short b = f2bf(dz);
-                v[i] = (short)b;
-                sD[w][(mt * 16 + 4 * q + i) * LDA + n] = b;
-            }
-            dzA[mt][nt] = bf16x4{v[0], v[1], v[2], v[3]};
+    bf16x4 dzA[4];  // dz2b as the A operand of dW2 (rows n, K = samples): the same lane layout
+    for (int nt = 0; nt < 4; nt++) {
+        const int n = nt * 16 + r;
+        short v[4];
+        for (int i = 0; i < 4; i++) {
+            const float h2 = tanhf(acc[0][nt][i] + s.b2[n]);
+            const float dz = dy[i] * s.w3[n] * (1.0f - h2 * h2);
+            gw3[nt] = __builtin_fmaf(dy[i], h2, gw3[nt]);
+            gb2[nt] += dz;
+            const unsigned short b = f2bf(dz);
+            v[i] = (short)b;
+            sD[w][(4 * q + i) * LDA + n] = b;
         }
+        dzA[nt] = bf16x4{v[0], v[1], v[2], v[3]};
+    }
     __syncthreads();
 
-    float* out = part + ((int64_t)blockIdx.x * 4 + w) * (kMlpParams + 1);
-    // dW2[n][k] = sum_s dz2b[s][n] h1b[s][k]: A = dz2b^T, B[s][k] = h1b from sA.  One matrix
-    // instruction sums 32 samples, two row tiles mt = 2t, 2t + 1: the lane's 8 K slots are
-    // samples 16 mt + 4 q + i (i = 0..3) of both tiles, which is exactly what it holds of
-    // dz2b in the accumulator layout, so A is two register tiles side by side.
+    float* out = red[w];
+    // dW2[n][k] = sum_s dz2b[s][n] h1b[s][k]: A = dz2b^T (the lane's K slots are its
+    // accumulator rows, samples 4 q + i), B[s][k] = h1b from sA; one K = 16 instruction
     for (int nt = 0; nt < 4; nt++)
         for (int kt = 0; kt < 4; kt++) {
-            f32x4 g = {0.0f, 0.0f, 0.0f, 0.0f};
-            for (int t = 0; t < 2; t++) {
-                short v[8];
-                for (int i = 0; i < 8; i++)
-                    v[i] = (short)sA[w][((2 * t + i / 4) * 16 + 4 * q + i % 4) * LDA + kt * 16 + r];
-                const s16x8 bv = s16x8{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]};
-                const s16x8 av = __builtin_shufflevector(dzA[2 * t][nt], dzA[2 * t + 1][nt], 0, 1, 2, 3, 4, 5, 6, 7);
-                g = mfma32(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv), g);
-            }
+            short v[4];
+            for (int i = 0; i < 4; i++) v[i] = (short)sA[w][(4 * q + i) * LDA + kt * 16 + r];
+            const f32x4 g = mfma16(dzA[nt], bf16x4{v[0], v[1], v[2], v[3]}, f32x4{0.0f, 0.0f, 0.0f, 0.0f});
             for (int i = 0; i < 4; i++) out[OFF_W2 + (nt * 16 + 4 * q + i) * H + kt * 16 + r] = g[i];
         }
     // dh1[s][k] = sum_n dz2b[s][n] bf(W2)[n][k]: A from sD (rows s), B[n][k] = w2t[k][n]
     float gw1[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}}, gb1[4] = {0, 0, 0, 0};
-    for (int mt = 0; mt < 4; mt++)
-        for (int kt = 0; kt < 4; kt++) {
-            f32x4 g = {0.0f, 0.0f, 0.0f, 0.0f};
-            for (int nk = 0; nk < 2; nk++)
-                g = mfma32(lds8(&sD[w][(mt * 16 + r) * LDA + nk * 32 + 8 * q]),
-                           lds8(&s.w2t[(kt * 16 + r) * LDA + nk * 32 + 8 * q]), g);
-            // dz1 = dh1 (1 - h1^2), with h1 recomputed from the sample's x (padding samples have dz2 = 0)
-            const int k = kt * 16 + r;
-            for (int i = 0; i < 4; i++) {
-                const int sl = mt * 16 + 4 * q + i;
-                const float xa = sX[w][sl][0], xb = sX[w][sl][1];
-                const float z1 = __builtin_fmaf(s.w1[2 * k], xa, __builtin_fmaf(s.w1[2 * k + 1], xb, 0.0f)) + s.b1[k];
-                const float h1 = tanhf(z1);
-                const float dz1 = g[i] * (1.0f - h1 * h1);
-                gw1[kt][0] = __builtin_fmaf(dz1, xa, gw1[kt][0]);
-                gw1[kt][1] = __builtin_fmaf(dz1, xb, gw1[kt][1]);
-                gb1[kt] += dz1;
-            }
+    for (int kt = 0; kt < 4; kt++) {
+        f32x4 g = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int nk = 0; nk < 2; nk++)
+            g = mfma32(lds8(&sD[w][r * LDA + nk * 32 + 8 * q]), lds8(&s.w2t[(kt * 16 + r) * LDA + nk * 32 + 8 * q]),
+                       g);
+        // dz1 = dh1 (1 - h1^2), with h1 recomputed from the sample's x (padding samples have dz2 = 0)
+        const int k = kt * 16 + r;
+        for (int i = 0; i < 4; i++) {
+            const int sl = 4 * q + i;
+            const float xa = sX[w][sl][0], xb = sX[w][sl][1];
+            const float z1 = __builtin_fmaf(s.w1[2 * k], xa, __builtin_fmaf(s.w1[2 * k + 1], xb, 0.0f)) + s.b1[k];
+            const float h1 = tanhf(z1);
+            const float dz1 = g[i] * (1.0f - h1 * h1);
+            gw1[kt][0] = __builtin_fmaf(dz1, xa, gw1[kt][0]);
+            gw1[kt][1] = __builtin_fmaf(dz1, xb, gw1[kt][1]);
+            gb1[kt] += dz1;
         }
+    }
     // column sums over the 4 row groups (lanes r, r + 16, r + 32, r + 48)
     for (int nt = 0; nt < 4; nt++) {
         for (int o = 16; o < 64; o <<= 1) {
@@ -277,19 +286,22 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ P, c
             out[OFF_B1 + n] = gb1[nt];
         }
     }
-    // db3 = sum dy (one value per sample: lanes with r == 0 hold 16 samples each)
+    // db3 = sum dy (one value per sample: lanes with r == 0 hold 4 samples each)
     float db3 = 0.0f;
     if (r == 0)
-        for (int mt = 0; mt < 4; mt++)
-            for (int i = 0; i < 4; i++) db3 += dy[mt][i];
+        for (int i = 0; i < 4; i++) db3 += dy[i];
     for (int o = 1; o < 64; o <<= 1) db3 += __shfl_xor(db3, o, 64);
     if (l == 0) {
         out[OFF_B3] = db3;
         out[kMlpParams] = sq;
     }
+    __syncthreads();
+    // the block's partial: the four wavefronts' sums in a fixed order
+    float* dst = part + (int64_t)blockIdx.x * (kMlpParams + 1);
+    for (int i = threadIdx.x; i <= kMlpParams; i += blockDim.x) dst[i] = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
 }
 
-// grad[p] = sum over wavefronts of part[w][p] (fixed order); loss = sum sq / B.
+// grad[p] = sum over blocks of part[w][p] (fixed order); loss = sum sq / B.
 // The partials are loaded kBatch at a time before they are added (in order),
 // so their latencies overlap: a training batch has few wavefronts of partials
 // per thread, and one load in flight at a time left the kernel latency-bound.
@@ -363,7 +375,7 @@ __global__ __launch_bounds__(256) void k_con2prim_seeded(C2PArgs<double> a, EosT
         const float x1 = ((float)(sqrt(M2) / E) - nrm.in_shift[1]) * nrm.in_scale[1];
         f32x4 acc[4][4];
         float yv[4][4];
-        mlp_forward_wave(s, sA[w], x0, x1, acc, yv);
+        mlp_forward_wave<4>(s, sA[w], x0, x1, acc, yv);
         if ((l & 15) == 0)
             for (int mt = 0; mt < 4; mt++)
                 for (int k = 0; k < 4; k++) sy[w][mt * 16 + 4 * (l >> 4) + k] = yv[mt][k];
@@ -425,18 +437,18 @@ hipError_t mlp_forward(const float* P, const float* X, int64_t B, float* y, hipS
     return hipGetLastError();
 }
 
-int64_t mlp_grad_partials(int64_t B) { return ((B + 255) / 256) * 4; }
+int64_t mlp_grad_partials(int64_t B) { return (B + 63) / 64; }   // one per block of 64 samples
 
 hipError_t mlp_grad(const float* P, const float* X, const float* T, int64_t B, float* part, float* grad, float* loss,
                     hipStream_t s)
 {
     if (B <= 0) return hipErrorInvalidValue;
-    const int64_t blocks = (B + 255) / 256;
+    const int64_t blocks = mlp_grad_partials(B);
     hipLaunchKernelGGL(k_mlp_grad, dim3((unsigned)blocks), dim3(256), 0, s, P, X, T, B, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_mlp_reduce, dim3((kMlpParams + 1 + 255) / 256), dim3(256), 0, s, part,
-                       (int)(blocks * 4), B, grad, loss);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((kMlpParams + 1 + 255) / 256), dim3(256), 0, s, part, (int)blocks, B,
+                       grad, loss);
     return hipGetLastError();
 }
 

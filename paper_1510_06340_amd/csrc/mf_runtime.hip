@@ -809,11 +809,11 @@ int check_desc(const mf_grid_desc& d)
 }  // namespace
 
 // Partial gradients of mf_mlp_grad_noalloc: one row of MF_MLP_PARAMS + 1 floats per
-// wavefront of the gradient kernel, for up to MF_MLP_NOALLOC_MAX_N samples.  Every
-// device holds its own copy; host code reaches it only through the address that
-// hipGetSymbolAddress returns on that device (the name itself is a host stand-in).
-static constexpr int64_t kNoallocFloats =
-    ((int64_t)(MF_MLP_NOALLOC_MAX_N + 255) / 256) * 4 * (MF_MLP_PARAMS + 1);
+// block (64 samples) of the gradient kernel, for up to MF_MLP_NOALLOC_MAX_N samples
+// (1.1 MB).  Every device holds its own copy; host code reaches it only through the
+// address that hipGetSymbolAddress returns on that device (the name itself is a
+// host stand-in).
+static constexpr int64_t kNoallocFloats = ((int64_t)(MF_MLP_NOALLOC_MAX_N + 63) / 64) * (MF_MLP_PARAMS + 1);
 static __device__ __align__(256) float scratch[kNoallocFloats];
 
 namespace {
