@@ -62,7 +62,7 @@ def test_piece_lookup_at_every_node():
     from paper_1510_06340_amd import mf
     e_nodes = np.asarray(TABLE[0])
     E = np.concatenate([e_nodes, np.nextafter(e_nodes, 0.0), np.nextafter(e_nodes, np.inf),
-                        [1e-6, 5e-4, 2e3, 1e5]])
+                        [1e-6, 5e-4, 2e3, 1e5, 1e20]])   # 1e20: beyond t < 1 of the last piece
     n = E.size
     U = np.zeros((4, 1, 1, n))
     U[0, 0, 0] = E
@@ -125,3 +125,30 @@ def test_crossover_192_full_size_one_step():
     Uo, sto = oracle.step(oracle.Problem.from_workload(w, table=TABLE), U, w.dt, 1)
     assert max_rel_err(Ug, Uo) <= 1e-10
     assert st["n_bad"] == 0
+
+
+def test_results_do_not_depend_on_the_work_decomposition():
+    """Each thread caches the last table piece it loaded, so which pieces a thread has seen
+    depends on how the sweeps are cut into work units.  The cache is keyed by the first-guess
+    piece, so results must not: runs with other x chunk and y/z segment lengths (and the
+    batched tile queue) are bitwise equal to the default run."""
+    w = I.crossover_workloads(n_events=1, n=48, steps=3)[0]
+    w.n = (48, 41, 37)
+    U = I.initial_state(w)
+    ref, st = gpu_run(w, U, eos_table=TABLE)
+    assert st["newton_iters"] > 0
+    for seg in ((1, 3, 5), (5, 16, 2), (13, 41, 37)):
+        Ug, _ = gpu_run(w, U, eos_table=TABLE, tuning=(seg, 256))
+        assert np.array_equal(Ug, ref), seg
+    import torch
+    from helpers import from_dev
+    dev = to_dev(U)
+    from paper_1510_06340_amd import mf
+    g = mf.Grid([mf.desc_from_workload(w)], [dev])
+    try:
+        g.set_eos_table(*TABLE)
+        g.batch_step([w.dt], w.steps)
+        torch.cuda.synchronize()
+        assert np.array_equal(from_dev(dev, U.shape[1:]), ref)
+    finally:
+        g.free()
