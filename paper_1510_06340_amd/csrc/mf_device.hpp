@@ -142,6 +142,8 @@ struct Counts {
 template <typename T> struct EosIdeal {
     static constexpr int kWaves = 4;  // sweep kernels fit 128 VGPRs without spilling
     static constexpr bool kLoadLAhead = false;  // no gain at 4 waves; FP32 would lose a wave
+    static constexpr int kCacheDoubles = 1;  // no lookup cache
+    __device__ __forceinline__ void bind_cache(double*) const {}
     T c;    // cs2
     T qh;   // (1 + cs2) / 2
     T q2q;  // (1 + cs2)^2 / 4
@@ -331,8 +333,21 @@ struct EosTable {
     // piece takes it from registers and issues no loads.  The cache is keyed
     // by the first guess, so every lane evaluates the piece it would have
     // loaded: results do not depend on the cache's history.
+    // The piece lives in a per-thread LDS slot (6 doubles, 256 apart), which the
+    // kernel binds: kept in registers, the compiler copied it at every lookup.
+    static constexpr int kCacheDoubles = 6 * 256;
     mutable int32_t ck = -1;
-    mutable double2 ca, cb, cc;
+    mutable double* cl = nullptr;
+    __device__ __forceinline__ void bind_cache(double* lds) const { cl = lds + threadIdx.x; }
+    __device__ __forceinline__ void put(const double2& a, const double2& b, const double2& c) const
+    {
+        cl[0] = a.x; cl[256] = a.y; cl[512] = b.x; cl[768] = b.y; cl[1024] = c.x; cl[1280] = c.y;
+    }
+    __device__ __forceinline__ double cached_cubic(double e, double& p, double& dp) const
+    {
+        const double2 a = {cl[0], cl[256]}, b = {cl[512], cl[768]}, c = {cl[1024], cl[1280]};
+        return cubic(e, a, b, c, p, dp);
+    }
 
     // Piece k: records 3k .. 3k + 2 (the table is far below 4 GiB, so a 32-bit byte offset).
     __device__ __forceinline__ const double2* piece_ptr(int k) const
@@ -382,14 +397,16 @@ struct EosTable {
     {
         if (log_uniform) {
             const int k = guess_piece(e);
+            uint64_t off;
             if (lanes_where(k != ck) != 0) {   // some lane needs another piece
                 const double2* r = piece_ptr(k);
-                ca = r[0];
-                cb = r[1];
-                cc = r[2];
+                const double2 a = r[0], b = r[1], c = r[2];
+                put(a, b, c);
                 ck = k;
+                off = outside(cubic(e, a, b, c, p, dp));
+            } else {
+                off = outside(cached_cubic(e, p, dp));
             }
-            const uint64_t off = outside(cubic(e, ca, cb, cc, p, dp));
             if (off != 0) {
                 if (lane_in(off)) walk(e, k, p, dp);
             }
@@ -420,13 +437,11 @@ struct EosTable {
                 const double2 aB = rB[0], bB = rB[1], cB = rB[2];
                 offA = outside(cubic(eA, aA, bA, cA, pA, dpA));
                 offB = outside(cubic(eB, aB, bB, cB, pB, dpB));
-                ca = aB;
-                cb = bB;
-                cc = cB;
+                put(aB, bB, cB);
                 ck = kB;
             } else {
-                offA = outside(cubic(eA, ca, cb, cc, pA, dpA));
-                offB = outside(cubic(eB, ca, cb, cc, pB, dpB));
+                offA = outside(cached_cubic(eA, pA, dpA));
+                offB = outside(cached_cubic(eB, pB, dpB));
             }
             if ((offA | offB) != 0) {
                 if (lane_in(offA)) walk(eA, kA, pA, dpA);
@@ -709,6 +724,8 @@ struct EosTable {
 struct EosGamma {
     static constexpr int kWaves = 3;            // five components: more live state per interface
     static constexpr bool kLoadLAhead = false;
+    static constexpr int kCacheDoubles = 1;  // no lookup cache
+    __device__ __forceinline__ void bind_cache(double*) const {}
     static constexpr int kMaxIter = 60;
     static constexpr double kTol = 1e-10;
     double gm1;    // gamma - 1

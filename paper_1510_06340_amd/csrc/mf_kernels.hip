@@ -309,6 +309,8 @@ constexpr int sweep_waves()
 template <typename T, int D, int LIM, class Eos, bool JET, bool UNSPLIT = false, int NC = 4>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_waves<Eos, JET>()))) void k_sweep(SweepArgs<T> a, Eos eos)
 {
+    __shared__ double eos_cache[Eos::kCacheDoubles];
+    eos.bind_cache(eos_cache);
     const int64_t line = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     Counts cnt;
     T smax = T(0);
@@ -438,6 +440,8 @@ template <typename T, int LIM, class Eos, bool UNSPLIT = false, int NC = 4>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Eos::kWaves))) void k_sweep_x(SweepArgs<T> a, Eos eos)
 {
     __shared__ T carry[256 / 64][2 * NC];
+    __shared__ double eos_cache[Eos::kCacheDoubles];
+    eos.bind_cache(eos_cache);
     Counts cnt;
     T smax = T(0);
     sweep_x_wave<T, LIM, Eos, UNSPLIT, NC>(a, eos, ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6,
@@ -482,6 +486,8 @@ __device__ __forceinline__ void unsplit_axis(const UnsplitArgs<T>& a, const Eos&
 template <typename T, int LIM, class Eos>
 __global__ __launch_bounds__(256) void k_unsplit_delta(UnsplitArgs<T> a, Eos eos)
 {
+    __shared__ double eos_cache[Eos::kCacheDoubles];
+    eos.bind_cache(eos_cache);
     const int64_t per = gridDim.x / 8;
     const int64_t chunk = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     const int64_t col = chunk * blockDim.x + threadIdx.x;
@@ -542,6 +548,8 @@ void k_batch_sweep(const SweepArgs<T>* __restrict__ tab, const int64_t* __restri
                    unsigned int* counter, Eos eos)
 {
     __shared__ int64_t sh_tile;
+    __shared__ double eos_cache[Eos::kCacheDoubles];
+    eos.bind_cache(eos_cache);
     const int64_t total = tile_start[ne];
     for (;;) {
         if (threadIdx.x == 0) sh_tile = (int64_t)atomicAdd(counter, 1u);
@@ -591,6 +599,8 @@ __global__ void k_fill_u32(unsigned int* p, int n, unsigned int v)
 template <typename T, class Eos, int NC = 4>
 __global__ __launch_bounds__(256) void k_con2prim(C2PArgs<T> a, Eos eos)
 {
+    __shared__ double eos_cache[Eos::kCacheDoubles];
+    eos.bind_cache(eos_cache);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     Counts cnt;
     if (i < a.n) {

@@ -357,6 +357,8 @@ __global__ __launch_bounds__(256) void k_con2prim_seeded(C2PArgs<double> a, EosT
     __shared__ MlpShared s;
     __shared__ __align__(16) unsigned short sA[4][64 * LDA];
     __shared__ float sy[4][64];
+    __shared__ double eos_cache[EosTable::kCacheDoubles];
+    eos.bind_cache(eos_cache);
     if (mode == 1) load_shared(P, s);
     __syncthreads();
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
