@@ -16,6 +16,7 @@
 // k_batch_sweep runs the same per-thread code for many events from one
 // persistent launch over a tile queue.
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include <algorithm>
 
@@ -328,10 +329,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_waves
 // writes L for the cell on its left.  All loads and stores are coalesced.
 // A wavefront owns items [s, s + 64 * seg) and starts two items early.
 // ---------------------------------------------------------------------------
-// The x sweep evaluates the face fluxes one after the other: paired table
-// lookups (flux2) need about 14 more registers, which costs the x sweep a
-// wavefront per SIMD (four to three) and more time than the overlap saves.
-constexpr bool kPairX = false;
+// The x sweep evaluates the face fluxes one after the other for p = c e (its
+// five wavefronts per SIMD hide the latency); with the table EoS it pairs the
+// lookups (flux2), which since the piece cache moved to LDS still fits four
+// wavefronts per SIMD.
+template <class Eos>
+constexpr bool kPairX = std::is_same<Eos, EosTable>::value;
 
 // Wavefront 'wave' of the x sweep: items [wave * 64 * seg, ...) of the row stream.
 // carry: this wavefront's 2 NC LDS slots, through which lane 63 hands its right
@@ -392,7 +395,7 @@ __device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& e
                 load_dl(a.dl + e, a.dl_n, d);
                 unsplit_faces<LIM>(w0, w1, w2, d, ULt, URt);
             } else {
-                hancock<0, LIM, kPairX, NC>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, cnt);
+                hancock<0, LIM, kPairX<Eos>, NC>(w0, w1, w2, a.ac.half_lam, ULt, URt, eos, cnt);
             }
             T URl[NC];
 #pragma unroll
@@ -402,7 +405,7 @@ __device__ __forceinline__ void sweep_x_wave(const SweepArgs<T>& a, const Eos& e
             for (int c = 0; c < NC; c++) F[c] = T(0);
             if (valid & (x >= 0) & (it >= s - 1)) {   // interface x - 1/2
                 cnt.w = (it >= s) ? 1u : 0u;
-                musta<0, kPairX, NC>(URl, ULt, a.k, a.ac, F, eos, cnt);
+                musta<0, kPairX<Eos>, NC>(URl, ULt, a.k, a.ac, F, eos, cnt);
             }
             T Fl[NC];
 #pragma unroll
