@@ -239,15 +239,24 @@ __device__ __forceinline__ void sweep_line(const SweepArgs<T>& a, const Eos& eos
         const int64_t ij = base + (int64_t)j * sd;
         const bool body = j >= s0;
         constexpr int MODE = sweep_mode<D>();
-        // With Eos::kLoadLAhead the y sweep's L so far is loaded before the
-        // cell's work, whose latency it hides behind (the z sweep has no
-        // registers to spare)
-        constexpr bool early_L = MODE == SW_ACCUM && Eos::kLoadLAhead;
-        T Lp[NC];
+        // With Eos::kLoadLAhead the L so far (and, in the z sweep, the stage's
+        // u0) is loaded before the cell's work, whose latency hides it; the
+        // jet's z sweep has no registers to spare for it
+        constexpr bool early_L =
+            Eos::kLoadLAhead && (MODE == SW_ACCUM || (MODE == SW_FINAL && !JET));
+        T Lp[NC], ub[NC];
 #pragma unroll
-        for (int c = 0; c < NC; c++) Lp[c] = T(0);
+        for (int c = 0; c < NC; c++) {
+            Lp[c] = T(0);
+            ub[c] = T(0);
+        }
         if constexpr (early_L) {
-            if (body) loadn<NC>((const T* const*)a.L, ij, Lp);
+            if (body) {
+                loadn<NC>((const T* const*)a.L, ij, Lp);
+                if constexpr (MODE == SW_FINAL) {
+                    if (a.kind != RK_FIRST) loadn<NC>(a.u0, ij, ub);
+                }
+            }
         }
         // the jet source of cell j, evaluated here where few values are live
         T SE = T(0);
@@ -284,11 +293,9 @@ __device__ __forceinline__ void sweep_line(const SweepArgs<T>& a, const Eos& eos
             continue;
         }
 
-        T Ld[NC], ub[NC];
-#pragma unroll
-        for (int c = 0; c < NC; c++) ub[c] = T(0);
+        T Ld[NC];
         if constexpr (MODE != SW_WRITE && !early_L) loadn<NC>((const T* const*)a.L, ij, Lp);
-        if constexpr (MODE == SW_FINAL) {
+        if constexpr (MODE == SW_FINAL && !early_L) {
             if (a.kind != RK_FIRST) loadn<NC>(a.u0, ij, ub);
         }
 #pragma unroll
