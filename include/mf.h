@@ -155,7 +155,7 @@ int mf_grid_init(mf_grid_t* out, const mf_grid_desc* descs, int32_t n_events,
  * index gamma in [1, 2] passed as cs2 (gamma = 1: pressureless dust); needs
  * MF_FLAG_CHARGE.  con2prim solves the fixed point of Sec. 2.6 for p by
  * safeguarded Newton; cold gas (p = 0) is exact.
- * MF_EOS_TABLE: n_tab >= 2 host nodes (e_tab strictly increasing, > 0;
+ * MF_EOS_TABLE: n_tab >= 3 host nodes (e_tab strictly increasing, > 0;
  * p_tab non-decreasing, >= 0, p < e) interpolated by a monotone piecewise
  * cubic; below e_tab[0] p = p_tab[0] e / e_tab[0], above the last node linear
  * with the end slope.  Fast interval lookup assumes log-uniform nodes and
