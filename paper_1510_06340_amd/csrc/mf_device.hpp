@@ -253,6 +253,12 @@ template <typename T> struct EosIdeal {
         flux<D, NC>(uA, FA, cnt);
         flux<D, NC>(uB, FB, cnt);
     }
+    // Flux of a state formed from the last pair (the closed form needs no start).
+    template <int D, int NC = 4>
+    __device__ __forceinline__ void flux_near(const T u[], T F[], Counts& cnt) const
+    {
+        flux<D, NC>(u, F, cnt);
+    }
 
     __device__ __forceinline__ void prim(const T u[], T& e, T& p, T v[3], T& cs2, Counts& cnt) const
     {
@@ -653,6 +659,12 @@ struct EosTable {
         assemble<D>(E, Mx, My, Mz, p, live, F);
         unscale(scaled, F);
     }
+    // Flux of a state formed from the last pair (the solve starts as in flux).
+    template <int D, int NC = 4>
+    __device__ __forceinline__ void flux_near(const double u[], double F[], Counts& cnt) const
+    {
+        flux<D, NC>(u, F, cnt);
+    }
 
     // Fluxes of two independent states, computed as flux() does but with the
     // first table lookups of both issued together (eval2): in the sweeps the
@@ -754,15 +766,17 @@ struct EosGamma {
         fp = gm1 * v2 * (1.0 - R * iw * W) - 1.0;
     }
 
-    // Pressure of a live state (E > 0, |M| < E, R >= 0).
-    __device__ __forceinline__ double pressure(double E, double M2, double R, Counts& cnt) const
+    // Pressure of a live state (E > 0, |M| < E, R >= 0).  The iteration starts
+    // from p0 where 0 < p0 < (gamma - 1) E (a neighbouring state's pressure),
+    // else from min(f(0), (gamma - 1) E).
+    __device__ __forceinline__ double pressure(double E, double M2, double R, Counts& cnt, double p0 = -1.0) const
     {
         if (M2 == 0.0) return gm1 * fmax(E - R, 0.0);
         double f, fp, iw;
         residual(E, M2, R, 0.0, f, fp, iw);
         if (!(f > 0.0)) return 0.0;   // cold gas
         double lo = 0.0, hi = gm1 * E;
-        double p = fmin(f, hi);
+        double p = (p0 > 0.0 && p0 < hi) ? p0 : fmin(f, hi);
         for (int it = 1;; it++) {
             residual(E, M2, R, p, f, fp, iw);
             // fp < 0 (about -1).  The hardware reciprocal (5e-8 relative) suffices: a
@@ -800,8 +814,10 @@ struct EosGamma {
         return true;
     }
 
+    // Flux of u; the pressure's iteration starts from p0 (see pressure).
+    // Returns the pressure, or -1 for a state evaluated scaled or zeroed.
     template <int D, int NC = 5>
-    __device__ __forceinline__ void flux(const double u[], double F[], Counts& cnt) const
+    __device__ __forceinline__ double flux_from(const double u[], double F[], Counts& cnt, double p0) const
     {
         static_assert(NC == 5, "the ideal gas needs the charge");
         // near-vacuum states are evaluated scaled up (con2prim of the ideal gas is scale invariant)
@@ -813,9 +829,9 @@ struct EosGamma {
         if (!fixup(E, Mx, My, Mz, M2, R, cnt)) {
 #pragma unroll
             for (int c = 0; c < 5; c++) F[c] = 0.0;
-            return;
+            return -1.0;
         }
-        const double p = pressure(E, M2, R, cnt);
+        const double p = pressure(E, M2, R, cnt, small ? -1.0 : p0);
         const double MD = (D == 0) ? Mx : ((D == 1) ? My : Mz);
         const double vD = MD * Math<double>::rcp(E + p);
         F[0] = MD;  // (E + p) v_D
@@ -827,15 +843,38 @@ struct EosGamma {
         if (small) {
 #pragma unroll
             for (int c = 0; c < 5; c++) F[c] = F[c] * down_scale<double>();
+            return -1.0;
         }
+        return p;
     }
 
+    template <int D, int NC = 5>
+    __device__ __forceinline__ void flux(const double u[], double F[], Counts& cnt) const
+    {
+        flux_from<D, NC>(u, F, cnt, -1.0);
+    }
+
+    // The two states of a pair (the faces of one cell, or the two sides of an
+    // interface) are close where the flow is smooth: B's iteration starts
+    // from A's pressure.  The mean of the two pressures is kept for the
+    // state that the next flux_near call forms from the pair.
+    mutable double p_pair = -1.0;
     template <int D, int NC = 5>
     __device__ __forceinline__ void flux2(const double uA[], const double uB[], double FA[], double FB[],
                                           Counts& cnt) const
     {
-        flux<D, NC>(uA, FA, cnt);
-        flux<D, NC>(uB, FB, cnt);
+        const double pA = flux_from<D, NC>(uA, FA, cnt, -1.0);
+        const double pB = flux_from<D, NC>(uB, FB, cnt, pA);
+        p_pair = (pA > 0.0 && pB > 0.0) ? 0.5 * (pA + pB) : -1.0;
+    }
+    // Flux of a state formed from the last flux2 pair (the Richtmyer state of a
+    // MUSTA stage): its iteration starts from the pair's mean pressure.  The
+    // start is used once, so the result depends only on that pair.
+    template <int D, int NC = 5>
+    __device__ __forceinline__ void flux_near(const double u[], double F[], Counts& cnt) const
+    {
+        flux_from<D, NC>(u, F, cnt, p_pair);
+        p_pair = -1.0;
     }
 
     // cs2 = gamma p / (e + p) (0 for cold gas).
@@ -1001,7 +1040,7 @@ __device__ __forceinline__ void musta(T UL[], T UR[], int k, const AxisConst<T>&
         flux_pair<D, T, Eos, PAIRED, NC>(eos, UL, UR, FL, FR, cnt);
 #pragma unroll
         for (int c = 0; c < NC; c++) Us[c] = T(0.5) * (UL[c] + UR[c]) - ac.half_alam * (FR[c] - FL[c]);
-        eos.template flux<D, NC>(Us, Flw, cnt);
+        eos.template flux_near<D, NC>(Us, Flw, cnt);
 #pragma unroll
         for (int c = 0; c < NC; c++)
             G[c] = fma(T(0.5), FL[c] + FR[c], fma(-ac.inv_2alam, UR[c] - UL[c], Flw[c]));

@@ -339,9 +339,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_waves
 // The x sweep evaluates the face fluxes one after the other for p = c e (its
 // five wavefronts per SIMD hide the latency); with the table EoS it pairs the
 // lookups (flux2), which since the piece cache moved to LDS still fits four
-// wavefronts per SIMD.
+// wavefronts per SIMD, and with the ideal gas it takes the pairs so that the
+// pressure iterations start from the pair's neighbour.
 template <class Eos>
-constexpr bool kPairX = std::is_same<Eos, EosTable>::value;
+constexpr bool kPairX = std::is_same<Eos, EosTable>::value || std::is_same<Eos, EosGamma>::value;
 
 // Wavefront 'wave' of the x sweep: items [wave * 64 * seg, ...) of the row stream.
 // carry: this wavefront's 2 NC LDS slots, through which lane 63 hands its right
