@@ -246,8 +246,8 @@ template <typename T> struct EosIdeal {
         }
     }
 
-    // Fluxes of two independent states.
-    template <int D, int NC = 4>
+    // Fluxes of two independent states (CHAIN: see EosGamma::flux2).
+    template <int D, int NC = 4, bool CHAIN = false>
     __device__ __forceinline__ void flux2(const T uA[], const T uB[], T FA[], T FB[], Counts& cnt) const
     {
         flux<D, NC>(uA, FA, cnt);
@@ -669,7 +669,8 @@ struct EosTable {
     // Fluxes of two independent states, computed as flux() does but with the
     // first table lookups of both issued together (eval2): in the sweeps the
     // lookups are L2 hits whose latency would otherwise be paid twice.
-    template <int D, int NC = 4>
+    // (CHAIN: see EosGamma::flux2; the table solves start as in flux.)
+    template <int D, int NC = 4, bool CHAIN = false>
     __device__ __forceinline__ void flux2(const double uA[], const double uB[], double FA[], double FB[],
                                           Counts& cnt) const
     {
@@ -857,15 +858,24 @@ struct EosGamma {
     // The two states of a pair (the faces of one cell, or the two sides of an
     // interface) are close where the flow is smooth: B's iteration starts
     // from A's pressure.  The mean of the two pressures is kept for the
-    // state that the next flux_near call forms from the pair.
+    // state that the next flux_near call forms from the pair.  With CHAIN,
+    // A's iteration starts from the previous pair's A: the pairs of a MUSTA
+    // solve follow the Hancock pair of the interface's right-hand cell, whose
+    // A is that cell's left face, at the same interface; each later stage's A
+    // is the predictor's update of the one before.  The sweeps evaluate that
+    // Hancock pair right before the interface's MUSTA solve, so every start
+    // comes from the same interface and results do not depend on the work
+    // decomposition.
     mutable double p_pair = -1.0;
-    template <int D, int NC = 5>
+    mutable double p_first = -1.0;
+    template <int D, int NC = 5, bool CHAIN = false>
     __device__ __forceinline__ void flux2(const double uA[], const double uB[], double FA[], double FB[],
                                           Counts& cnt) const
     {
-        const double pA = flux_from<D, NC>(uA, FA, cnt, -1.0);
+        const double pA = flux_from<D, NC>(uA, FA, cnt, CHAIN ? p_first : -1.0);
         const double pB = flux_from<D, NC>(uB, FB, cnt, pA);
         p_pair = (pA > 0.0 && pB > 0.0) ? 0.5 * (pA + pB) : -1.0;
+        p_first = pA;
     }
     // Flux of a state formed from the last flux2 pair (the Richtmyer state of a
     // MUSTA stage): its iteration starts from the pair's mean pressure.  The
@@ -965,12 +975,13 @@ __device__ __forceinline__ T half_slope(T a, T b)
 // U^R = U + Delta/2, both advanced by (dt/2dx)(F(U^L) - F(U^R))).
 // ---------------------------------------------------------------------------
 // PAIRED: evaluate the two face fluxes with Eos::flux2 (overlapped table
-// lookups; more registers), else one after the other.
-template <int D, typename T, class Eos, bool PAIRED, int NC = 4>
+// lookups; more registers), else one after the other.  CHAIN: the pair
+// continues the previous pair's interface (Eos::flux2).
+template <int D, typename T, class Eos, bool PAIRED, int NC = 4, bool CHAIN = false>
 __device__ __forceinline__ void flux_pair(const Eos& eos, const T uA[], const T uB[], T FA[], T FB[], Counts& cnt)
 {
     if constexpr (PAIRED) {
-        eos.template flux2<D, NC>(uA, uB, FA, FB, cnt);
+        eos.template flux2<D, NC, CHAIN>(uA, uB, FA, FB, cnt);
     } else {
         eos.template flux<D, NC>(uA, FA, cnt);
         eos.template flux<D, NC>(uB, FB, cnt);
@@ -1037,7 +1048,7 @@ __device__ __forceinline__ void musta(T UL[], T UR[], int k, const AxisConst<T>&
 {
     for (int l = 1;; l++) {
         T FL[NC], FR[NC], Us[NC], Flw[NC];
-        flux_pair<D, T, Eos, PAIRED, NC>(eos, UL, UR, FL, FR, cnt);
+        flux_pair<D, T, Eos, PAIRED, NC, true>(eos, UL, UR, FL, FR, cnt);
 #pragma unroll
         for (int c = 0; c < NC; c++) Us[c] = T(0.5) * (UL[c] + UR[c]) - ac.half_alam * (FR[c] - FL[c]);
         eos.template flux_near<D, NC>(Us, Flw, cnt);
