@@ -769,15 +769,32 @@ struct EosGamma {
 
     // Pressure of a live state (E > 0, |M| < E, R >= 0).  The iteration starts
     // from p0 where 0 < p0 < (gamma - 1) E (a neighbouring state's pressure),
-    // else from min(f(0), (gamma - 1) E).
+    // else from min(f(0), (gamma - 1) E) once f(0) > 0 has ruled out cold gas.
     __device__ __forceinline__ double pressure(double E, double M2, double R, Counts& cnt, double p0 = -1.0) const
     {
         if (M2 == 0.0) return gm1 * fmax(E - R, 0.0);
         double f, fp, iw;
-        residual(E, M2, R, 0.0, f, fp, iw);
-        if (!(f > 0.0)) return 0.0;   // cold gas
         double lo = 0.0, hi = gm1 * E;
-        double p = (p0 > 0.0 && p0 < hi) ? p0 : fmin(f, hi);
+        double p;
+        if (p0 > 0.0 && p0 < hi) {
+            // The first Newton step from p0.  A step accepted at a positive
+            // p needs no cold-gas test: f decreases, so f(0) > f(root) = 0.
+            residual(E, M2, R, p0, f, fp, iw);
+            const double dp = f * __builtin_amdgcn_rcp(fp);
+            p = p0 - dp;
+            cnt.iters += cnt.w;
+            if (fabs(dp) <= kTol * (E + p0) && p > 0.0) return p;
+            if (f > 0.0) lo = p0;
+            else hi = p0;
+            double f0, fp0, iw0;
+            residual(E, M2, R, 0.0, f0, fp0, iw0);
+            if (!(f0 > 0.0)) return 0.0;   // cold gas
+            if (!(p > lo && p < hi)) p = 0.5 * (lo + hi);
+        } else {
+            residual(E, M2, R, 0.0, f, fp, iw);
+            if (!(f > 0.0)) return 0.0;   // cold gas
+            p = fmin(f, hi);
+        }
         for (int it = 1;; it++) {
             residual(E, M2, R, p, f, fp, iw);
             // fp < 0 (about -1).  The hardware reciprocal (5e-8 relative) suffices: a
