@@ -8,6 +8,8 @@
 * With p = e/3 the charge is passive: E and M bitwise those of the run without it, R
   within 1e-10 of the oracle and conserved on a periodic grid.
 * con2prim with the charge against the oracle; uniform states bitwise; thin grids.
+* Results do not depend on the x chunk and y/z segment lengths (the warm-started
+  pressure iterations take their starts from the same interface only).
 """
 import math
 
@@ -180,6 +182,25 @@ def test_con2prim_with_charge_matches_oracle():
     np.testing.assert_allclose(pg[2:5], po[2:5], rtol=0, atol=1e-13)
     assert np.all(np.abs(pg[5] - po[5]) <= 1e-12 * R)
     assert stats[1] == 0 and int(it.max().item()) < 40
+
+
+def test_pressure_starts_do_not_depend_on_the_work_decomposition():
+    """The ideal gas's pressure iterations start from neighbouring states of the same
+    interface (the pair's other state, the previous pair of the MUSTA solve, the Hancock pair
+    of the interface's right-hand cell), never from wherever a work unit began: runs with other
+    x chunk and y/z segment lengths are bitwise equal (events with the charge step per event
+    only)."""
+    rng = np.random.default_rng(31)
+    n = (37, 29, 23)
+    U = random_charged(rng, n, 0.6)
+    w = charged(I.Workload("t", n, (0.1, 0.1, 0.1), (0, 0, 0), (0, 1, 0), I.LIM_MC, 3, 3, 0.02, 3))
+    ref, st = gpu_run(w, U)
+    assert st["newton_iters"] > 0 and st["n_bad"] == 0
+    for seg in ((1, 3, 5), (5, 16, 2), (13, 29, 23)):
+        Ug, _ = gpu_run(w, U, tuning=(seg, 256))
+        assert np.array_equal(Ug, ref), seg
+    Uo, _ = oracle_run(w, U, w.steps)
+    assert max_rel_err(ref, Uo) <= 1e-11
 
 
 def test_uniform_state_and_thin_grids_with_charge():
