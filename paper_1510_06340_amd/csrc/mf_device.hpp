@@ -729,7 +729,8 @@ struct EosTable {
 //   f(p) = (gamma - 1)(e(p) - n(p)) - p,
 // which decreases in p (for gamma <= 2): f' = (gamma - 1) v^2 (1 - R W / (E + p)) - 1.
 // If f(0) <= 0 the gas is cold (p = 0, v = M / E).  Otherwise safeguarded
-// Newton on [0, (gamma - 1) E] from p = f(0): a step leaving the bracket
+// Newton on [0, (gamma - 1) E] from p = f(0), or from a neighbouring state's
+// pressure in the sweeps (flux2, flux_near): a step leaving the bracket
 // (which shrinks with the sign of f) is replaced by bisection; the solve stops
 // when the correction is below 1e-10 (E + p) and accepts it (quadratic
 // convergence leaves an error far below the rounding of f).
