@@ -771,13 +771,17 @@ struct EosGamma {
     // Pressure of a live state (E > 0, |M| < E, R >= 0).  The iteration starts
     // from p0 where 0 < p0 < (gamma - 1) E (a neighbouring state's pressure),
     // else from min(f(0), (gamma - 1) E) once f(0) > 0 has ruled out cold gas.
+    // STEP_FIRST takes the first step from p0 before the cold-gas test (which
+    // a converged positive step makes unnecessary); the x sweep, whose
+    // neighbouring states differ more, runs the test first (it measured faster).
+    template <bool STEP_FIRST = true>
     __device__ __forceinline__ double pressure(double E, double M2, double R, Counts& cnt, double p0 = -1.0) const
     {
         if (M2 == 0.0) return gm1 * fmax(E - R, 0.0);
         double f, fp, iw;
         double lo = 0.0, hi = gm1 * E;
         double p;
-        if (p0 > 0.0 && p0 < hi) {
+        if (STEP_FIRST && p0 > 0.0 && p0 < hi) {
             // The first Newton step from p0.  A step accepted at a positive
             // p needs no cold-gas test: f decreases, so f(0) > f(root) = 0.
             residual(E, M2, R, p0, f, fp, iw);
@@ -794,7 +798,7 @@ struct EosGamma {
         } else {
             residual(E, M2, R, 0.0, f, fp, iw);
             if (!(f > 0.0)) return 0.0;   // cold gas
-            p = fmin(f, hi);
+            p = (p0 > 0.0 && p0 < hi) ? p0 : fmin(f, hi);
         }
         for (int it = 1;; it++) {
             residual(E, M2, R, p, f, fp, iw);
@@ -850,7 +854,7 @@ struct EosGamma {
             for (int c = 0; c < 5; c++) F[c] = 0.0;
             return -1.0;
         }
-        const double p = pressure(E, M2, R, cnt, small ? -1.0 : p0);
+        const double p = pressure<(D > 0)>(E, M2, R, cnt, small ? -1.0 : p0);
         const double MD = (D == 0) ? Mx : ((D == 1) ? My : Mz);
         const double vD = MD * Math<double>::rcp(E + p);
         F[0] = MD;  // (E + p) v_D
