@@ -774,10 +774,18 @@ struct EosGamma {
     // STEP_FIRST takes the first step from p0 before the cold-gas test (which
     // a converged positive step makes unnecessary); the x sweep, whose
     // neighbouring states differ more, runs the test first (it measured faster).
+    // iwp returns 1 / (E + p) for the returned p.  After an accepted step it is
+    // the last residual's 1 / (E + p_k) carried to p = p_k - d to first order,
+    // iw (1 + d iw): d iw <= kTol, so the remainder (d iw)^2 is below 1e-20.
     template <bool STEP_FIRST = true>
-    __device__ __forceinline__ double pressure(double E, double M2, double R, Counts& cnt, double p0 = -1.0) const
+    __device__ __forceinline__ double pressure(double E, double M2, double R, Counts& cnt, double& iwp,
+                                               double p0 = -1.0) const
     {
-        if (M2 == 0.0) return gm1 * fmax(E - R, 0.0);
+        if (M2 == 0.0) {
+            const double p = gm1 * fmax(E - R, 0.0);
+            iwp = Math<double>::rcp(E + p);
+            return p;
+        }
         double f, fp, iw;
         double lo = 0.0, hi = gm1 * E;
         double p;
@@ -788,16 +796,25 @@ struct EosGamma {
             const double dp = f * __builtin_amdgcn_rcp(fp);
             p = p0 - dp;
             cnt.iters += cnt.w;
-            if (fabs(dp) <= kTol * (E + p0) && p > 0.0) return p;
+            if (fabs(dp) <= kTol * (E + p0) && p > 0.0) {
+                iwp = fma(iw * dp, iw, iw);
+                return p;
+            }
             if (f > 0.0) lo = p0;
             else hi = p0;
             double f0, fp0, iw0;
             residual(E, M2, R, 0.0, f0, fp0, iw0);
-            if (!(f0 > 0.0)) return 0.0;   // cold gas
+            if (!(f0 > 0.0)) {   // cold gas
+                iwp = iw0;
+                return 0.0;
+            }
             if (!(p > lo && p < hi)) p = 0.5 * (lo + hi);
         } else {
             residual(E, M2, R, 0.0, f, fp, iw);
-            if (!(f > 0.0)) return 0.0;   // cold gas
+            if (!(f > 0.0)) {   // cold gas
+                iwp = iw;
+                return 0.0;
+            }
             p = (p0 > 0.0 && p0 < hi) ? p0 : fmin(f, hi);
         }
         for (int it = 1;; it++) {
@@ -807,12 +824,19 @@ struct EosGamma {
             const double dp = f * __builtin_amdgcn_rcp(fp);
             double pn = p - dp;
             cnt.iters += cnt.w;
-            if (fabs(dp) <= kTol * (E + p)) return fmax(pn, 0.0);
+            if (fabs(dp) <= kTol * (E + p)) {
+                const double pr = fmax(pn, 0.0);
+                iwp = fma(iw * (p - pr), iw, iw);
+                return pr;
+            }
             if (f > 0.0) lo = p;
             else hi = p;
             if (!(pn > lo && pn < hi)) pn = 0.5 * (lo + hi);
             p = pn;
-            if (it >= kMaxIter) return p;
+            if (it >= kMaxIter) {
+                iwp = Math<double>::rcp(E + p);
+                return p;
+            }
         }
     }
 
@@ -854,9 +878,10 @@ struct EosGamma {
             for (int c = 0; c < 5; c++) F[c] = 0.0;
             return -1.0;
         }
-        const double p = pressure<(D > 0)>(E, M2, R, cnt, small ? -1.0 : p0);
+        double iw;
+        const double p = pressure<(D > 0)>(E, M2, R, cnt, iw, small ? -1.0 : p0);
         const double MD = (D == 0) ? Mx : ((D == 1) ? My : Mz);
-        const double vD = MD * Math<double>::rcp(E + p);
+        const double vD = MD * iw;
         F[0] = MD;  // (E + p) v_D
         F[1] = Mx * vD;
         F[2] = My * vD;
@@ -922,8 +947,8 @@ struct EosGamma {
             e = 0.0; p = 0.0; v[0] = 0.0; v[1] = 0.0; v[2] = 0.0; cs2 = 0.0;
             return;
         }
-        p = pressure(E, M2, R, cnt);
-        const double iw = Math<double>::rcp(E + p);
+        double iw;
+        p = pressure(E, M2, R, cnt, iw);
         v[0] = Mx * iw; v[1] = My * iw; v[2] = Mz * iw;
         e = E - M2 * iw;
         cs2 = p > 0.0 ? gam * p * Math<double>::rcp(e + p) : 0.0;
