@@ -79,6 +79,13 @@ def flops_per_cell_axis(k: int, limiter: int, c2p_flux: int = C2P_FLUX, nc: int 
     return recon + hancock + musta + nc * 2
 
 
+def gas_flops_per_cell_axis(k: int, limiter: int) -> float:
+    """The ideal gas with the charge, mean over the x, y and z sweeps: in y and z all solves per cell
+    but the Hancock pair's first (1 + 3k of 2 + 3k) skip the residual at p = 0 and the start."""
+    fx = flops_per_cell_axis(k, limiter, C2P_FLUX_GAS, nc=5)
+    return (fx + 2 * (fx - (1 + 3 * k) * GAS_WARM_SKIP)) / 3
+
+
 def flops_per_cell_stage(k: int, limiter: int) -> int:
     """Three axis sweeps, two L accumulations and the RK combine (12 on average)."""
     return 3 * flops_per_cell_axis(k, limiter) + 8 + 12
@@ -409,8 +416,7 @@ def main(argv=None):
     newton_flops = None
     if "gamma" in w.extra:
         # Newton iterations per sweep launch: those of the step after the timed ones, over its sweeps
-        fl_x = flops_per_cell_axis(w.k, w.limiter, C2P_FLUX_GAS, nc=5)
-        fl_axis = fl_x - 2 * GAS_WARM_SKIP * (1 + 3 * w.k) / 3   # mean of x, y and z
+        fl_axis = gas_flops_per_cell_axis(w.k, w.limiter)
         fl_launch = fl_axis * w.cells + NEWTON_ITER_FLOPS_GAS * st["newton_iters"] / (3 * w.rk)
         newton_flops = NEWTON_ITER_FLOPS_GAS
     elif table is None:
