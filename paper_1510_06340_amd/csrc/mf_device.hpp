@@ -867,13 +867,28 @@ struct EosGamma {
     __device__ __forceinline__ double flux_from(const double u[], double F[], Counts& cnt, double p0) const
     {
         static_assert(NC == 5, "the ideal gas needs the charge");
-        // near-vacuum states are evaluated scaled up (con2prim of the ideal gas is scale invariant)
-        const bool small = (u[0] > 0.0) & (u[0] < tiny_value<double>());
-        const double sc = small ? up_scale<double>() : 1.0;
-        double E = u[0] * sc, Mx = u[1] * sc, My = u[2] * sc, Mz = u[3] * sc;
-        const double R = u[4] * sc;
+        double E = u[0], Mx = u[1], My = u[2], Mz = u[3], R = u[4];
         double M2 = Mx * Mx + My * My + Mz * Mz;
-        if (!fixup(E, Mx, My, Mz, M2, R, cnt)) {
+        // The guards run only in wavefronts holding a state that needs one (the
+        // vote covers every case fixup handles): near-vacuum states are
+        // evaluated scaled up (con2prim of the ideal gas is scale invariant).
+        const double Mlim = mmax<double>() * E;
+        const uint64_t bad = lanes_where(!(E >= tiny_value<double>())) | lanes_where(!(E <= big_value<double>())) |
+                             lanes_where(!(M2 <= Mlim * Mlim)) | lanes_where(!(M2 <= big_value<double>())) |
+                             lanes_where(!(R >= 0.0)) | lanes_where(!(R <= big_value<double>()));
+        bool small = false, live = true;
+        if (bad != 0) {
+            if (lane_in(bad)) {
+                small = (E > 0.0) & (E < tiny_value<double>());
+                if (small) {
+                    E = E * up_scale<double>(); Mx = Mx * up_scale<double>(); My = My * up_scale<double>();
+                    Mz = Mz * up_scale<double>(); R = R * up_scale<double>();
+                    M2 = Mx * Mx + My * My + Mz * Mz;
+                }
+                live = fixup(E, Mx, My, Mz, M2, R, cnt);
+            }
+        }
+        if (!live) {
 #pragma unroll
             for (int c = 0; c < 5; c++) F[c] = 0.0;
             return -1.0;
